@@ -1,0 +1,160 @@
+"""Pins for the oracle's rollout, costs, weights and update (Alg. 1; Eqs. 5, 11, 12)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mppi
+from oracle import gp as G
+from paper_2411_03289_amd import workloads as W
+
+
+def test_weights_invariants():
+    rng = np.random.Generator(np.random.PCG64(1))
+    S = rng.uniform(0, 30, 4096)
+    w = mppi.weights(S, 1.0)
+    assert abs(w.sum() - 1.0) < 1e-15
+    np.testing.assert_allclose(mppi.weights(S + 1234.5, 1.0), w, rtol=1e-12)
+    np.testing.assert_allclose(mppi.weights(np.full(10, 3.3), 1.0), 0.1, rtol=1e-15)
+    w0 = mppi.weights(S, 1e-6)
+    assert w0[np.argmin(S)] == 1.0
+    tie = np.array([2.0, 1.0, 5.0, 1.0])
+    np.testing.assert_allclose(mppi.weights(tie, 1e-9), [0, 0.5, 0, 0.5], atol=1e-300)
+    np.testing.assert_allclose(mppi.weights(S, 1e12), 1.0 / S.size, rtol=1e-9)
+    # the exponential form: ratios are exp(-(S_i - S_j)/lambda)
+    assert w[0] / w[1] == pytest.approx(math.exp(-(S[0] - S[1]) / 1.0), rel=1e-12)
+
+
+def test_update_is_convex_combination():
+    rng = np.random.Generator(np.random.PCG64(2))
+    u = rng.uniform(-2, 2, size=(5, 100, 2))
+    w = mppi.weights(rng.uniform(0, 3, 100), 0.5)
+    U = mppi.update(w, u)
+    assert np.all(U <= u.max(axis=1) + 1e-15) and np.all(U >= u.min(axis=1) - 1e-15)
+    one = np.zeros(100)
+    one[37] = 1.0
+    np.testing.assert_array_equal(mppi.update(one, u), u[:, 37])
+
+
+def _straight_line_problem(T=40):
+    # GP data far from every query (zero mean, prior variance), almost no GP
+    # variance, no control noise, command equal to the start velocity: the
+    # robot drives straight up along X = 5 from the circle track's edge.
+    pr = W.small_problem(K=8, T=T, M=10, n_obs=0, seed_data=5)
+    pr.Z = pr.Z + 100.0
+    pr.log_sf[:] = math.log(1e-7)
+    pr.log_sn[:] = math.log(1e-7)
+    pr.params.update(sig_v=0.0, sig_w=0.0)
+    pr.x0 = np.array([5.0, 0.0, math.pi / 2, 2.0, 0.0])
+    pr.U0 = np.tile([2.0, 0.0], (T, 1))
+    pr.obstacles = np.array([[5.0, 2.0, 0.33], [-4.0, -4.0, 0.5]])
+    return pr
+
+
+def test_straight_line_scenario_costs_closed_form():
+    T = 40
+    pr = _straight_line_problem(T)
+    p = pr.params
+    Unew, S, w, tr = mppi.iteration(pr)
+    k = np.arange(T)
+    Y = 2.0 * p["dt"] * (k + 1)
+    np.testing.assert_allclose(tr.x[1:, 0, 1], Y, atol=1e-12)
+    d = np.hypot(5.0, Y) - 5.0
+    lane_exit = d > 1.0
+    collide = np.abs(Y - 2.0) <= 0.33
+    assert lane_exit.sum() == T - 33 and collide.sum() == 7
+    var = 2 * (1e-14 + 1e-14)
+    stage = (p["w_var"] * var + p["w_dev"] * d / 1.0 + p["w_lane"] * 0.9 ** k * lane_exit
+             + p["w_speed"] * (2.0 - 2.0) ** 2 + p["w_obs"] * collide)
+    np.testing.assert_allclose(tr.stage[:, 0], stage, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(S, stage.sum(), rtol=1e-12)
+    np.testing.assert_allclose(w, 1.0 / pr.K, rtol=1e-12)
+    np.testing.assert_allclose(Unew, pr.U0, rtol=1e-15)
+
+
+def test_speed_and_variance_terms_closed_form():
+    T = 25
+    pr = _straight_line_problem(T)
+    pr.obstacles = np.zeros((0, 3))
+    pr.log_sf[:] = math.log(0.4)          # prior variance everywhere: sf^2 + sn^2
+    pr.x0 = np.array([5.0, 0.0, math.pi / 2, 0.5, 0.0])
+    pr.U0 = np.tile([1.5, 0.0], (T, 1))
+    p = pr.params
+    _, S, _, tr = mppi.iteration(pr)
+    k = np.arange(T)
+    v = 1.5 + (0.5 - 1.5) * (1 - p["dt"] / p["tau_v"]) ** (k + 1)
+    np.testing.assert_allclose(tr.x[1:, 0, 3], v, rtol=1e-13)
+    np.testing.assert_allclose(tr.gp_var[:, 0, :], 0.16 + 1e-14, rtol=1e-12)
+    speed = p["w_speed"] * (p["v_des"] - v) ** 2
+    assert tr.obs_margin.min() == np.inf
+    ref = (p["w_var"] * 2 * (0.16 + 1e-14) + p["w_dev"] * tr.d_lane[:, 0] + speed
+           + p["w_lane"] * 0.9 ** k * (tr.lane_margin[:, 0] < 0))
+    np.testing.assert_allclose(S[0], ref.sum(), rtol=1e-12)
+
+
+def test_gp_zeroed_rollout_is_nominal_unicycle():
+    # The unicycle-only MPPI baseline: zero GP targets give zero residual mean.
+    pr = W.small_problem(K=32, T=15, M=20, seed_data=6, U_scale=1.0)
+    pr.y[:] = 0.0
+    _, tr = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    p = pr.params
+    np.testing.assert_array_equal(tr.gp_mean, 0.0)
+    x = np.tile(pr.x0, (pr.K, 1))
+    for k in range(pr.T):
+        u = tr.u[k]
+        x = np.stack([x[:, 0] + p["dt"] * x[:, 3] * np.cos(x[:, 2]),
+                      x[:, 1] + p["dt"] * x[:, 3] * np.sin(x[:, 2]),
+                      x[:, 2] + p["dt"] * x[:, 4],
+                      x[:, 3] + p["dt"] * (u[:, 0] - x[:, 3]) / p["tau_v"],
+                      x[:, 4] + p["dt"] * (u[:, 1] - x[:, 4]) / p["tau_w"]], axis=1)
+        np.testing.assert_allclose(tr.x[k + 1], x, rtol=1e-13, atol=1e-13)
+
+
+def test_subset_rollout_equals_full_rows():
+    pr = W.small_problem(K=64, T=8, M=16, seed_data=3, U_scale=0.5)
+    S, tr = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    ids = np.array([0, 5, 63, 17])
+    S2, tr2 = mppi.rollout(pr, pr.x0, pr.U0, pr.seed, sample_ids=ids)
+    np.testing.assert_array_equal(S2, S[ids])
+    np.testing.assert_array_equal(tr2.x, tr.x[:, ids])
+
+
+def test_zero_noise_update_returns_clipped_nominal():
+    pr = W.small_problem(K=16, T=6, M=12, seed_data=4)
+    pr.params.update(sig_v=0.0, sig_w=0.0)
+    pr.U0 = np.array([[3.0, 0.1], [-2.5, 1.0], [0.2, 0.3], [1.0, -4.0], [0, 0], [2, 2]])
+    Unew, S, w, _ = mppi.iteration(pr)
+    np.testing.assert_allclose(Unew, np.clip(pr.U0, -2, 2), rtol=1e-15)
+    np.testing.assert_allclose(S, S[0], rtol=1e-15)
+
+
+def test_small_lambda_selects_best_sample():
+    pr = W.small_problem(K=128, T=10, M=16, seed_data=8)
+    pr.params["lam"] = 1e-8
+    Unew, S, w, tr = mppi.iteration(pr)
+    np.testing.assert_allclose(Unew, tr.u[:, np.argmin(S)], rtol=1e-15)
+
+
+def test_closed_loop_applies_first_control_and_shifts():
+    pr = W.small_problem(K=32, T=6, M=12, seed_data=9)
+    xs, Us = mppi.closed_loop(pr, 3)
+    from oracle import dynamics as D
+    p = pr.params
+    x = pr.x0.copy()
+    U = pr.U0.copy()
+    gps = G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)
+    for t in range(3):
+        Unew, _, _, _ = mppi.iteration(pr, x, U, pr.seed_at(t), gps=gps)
+        np.testing.assert_array_equal(Us[t], Unew)
+        x = D.plant_step(x, Unew[0], p["dt"], p["tau_v"], p["tau_w"])[0]
+        np.testing.assert_array_equal(xs[t + 1], x)
+        U = np.concatenate([Unew[1:], Unew[-1:]])
+
+
+def test_flip_budget_counts_near_threshold_indicators():
+    pr = _straight_line_problem(40)
+    _, _, _, tr = mppi.iteration(pr)
+    # exactly-on-threshold decisions never occur here; a wide band catches them all
+    assert np.all(mppi.flip_budget(pr, tr, 1e-9) == 0.0)
+    wide = mppi.flip_budget(pr, tr, 10.0)
+    assert wide[0] == pytest.approx(np.sum(0.9 ** np.arange(40)) + 40.0, rel=1e-12)
