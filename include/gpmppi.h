@@ -1,0 +1,202 @@
+/*
+ * gpmppi.h - C ABI of the MI355X (gfx950) GP-augmented chance-constrained MPPI
+ * rollout library.
+ *
+ * Method: Trivedi et al., "Data-Driven Sampling Based Stochastic MPC for
+ * Skid-Steer Mobile Robot Navigation" (arXiv 2411.03289).  One controller
+ * iteration is Algorithm 1, Step 1: K sampled control sequences are rolled out
+ * over T steps through the dynamic unicycle with a GP residual (Eqs. 1-3, 6),
+ * the mean and covariance are propagated per sample (Eq. 10), the lane and
+ * obstacle chance constraints are tightened by the propagated position
+ * covariance (Eqs. 13-16), a stage cost built from Eqs. (11)-(12) is summed
+ * (Eq. 5), and the nominal sequence is replaced by the exponentially weighted
+ * average of the samples.
+ *
+ * Conventions for every entry point:
+ *  - Functions return a gpmppi_status; GPMPPI_OK is 0, errors are negative.
+ *    On error a message is available from gpmppi_last_error() (thread-local,
+ *    valid until the next call on the same thread).
+ *  - Host arrays (const double *, in init / set_gp) are read during the call
+ *    only; the caller keeps ownership.
+ *  - Device arrays (float *, uint32_t * with a _d suffix) are caller-owned
+ *    device allocations on the context's device, e.g. torch tensors.  Calls
+ *    that take a `stream` (a hipStream_t, NULL = the default stream) only
+ *    enqueue work: results are ready when that stream has reached them.
+ *  - All arguments are validated on the host before any device work is
+ *    enqueued; an invalid argument enqueues nothing.
+ *  - Results are deterministic: the same inputs and seed give bitwise
+ *    identical outputs (fixed-order reductions, no floating-point atomics).
+ *  - A context may be used from one host thread at a time; calls that share
+ *    a context and overlap on different streams race on its work buffers.
+ */
+#ifndef GPMPPI_H
+#define GPMPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GPMPPI_OK = 0,
+    GPMPPI_E_INVALID = -1,      /* bad size, pointer or parameter value */
+    GPMPPI_E_NOT_PD = -2,       /* K(Z,Z) + sn^2 I is not positive definite (no jitter is added) */
+    GPMPPI_E_HIP = -3,          /* a HIP runtime call failed */
+    GPMPPI_E_NOMEM = -4,        /* device allocation failed */
+    GPMPPI_E_NONFINITE = -5,    /* a host input holds NaN or Inf */
+    GPMPPI_E_UNSUPPORTED = -6   /* a size beyond the supported maximum (e.g. M > 1024) */
+} gpmppi_status;
+
+/* Arithmetic of the GP variance contraction k^T (K + sn^2 I)^-1 k, computed as
+ * ||W k||^2 with W = L^-1 on the matrix cores.  Kernel vectors, the GP mean,
+ * the dynamics, constraints and costs are FP32 in every form. */
+typedef enum {
+    GPMPPI_FP32 = 0,            /* FP32 operands, FP32 accumulation */
+    GPMPPI_BF16 = 1,            /* BF16 W and k, FP32 accumulation */
+    GPMPPI_BF16X3 = 2           /* hi+lo BF16 splits, three products, FP32 accumulation */
+} gpmppi_precision;
+
+typedef struct gpmppi_ctx gpmppi_ctx;   /* opaque; owns every device buffer it allocates */
+
+/* One residual GP (Sec. III-A: one GP per velocity output; Sec. IV-A: input
+ * (v, w, v_cmd, w_cmd)).  Squared-exponential ARD covariance
+ * k(a,b) = exp(2 log_sf) exp(-1/2 sum_d (a_d-b_d)^2 exp(-2 log_ell[d])),
+ * observation noise variance exp(2 log_sn). */
+typedef struct {
+    int32_t M;                  /* training / inducing points, 1 <= M <= 1024 */
+    const double *Z;            /* [M][4] row-major host array */
+    const double *y;            /* [M] host array of residual targets */
+    double log_ell[4];
+    double log_sf;
+    double log_sn;
+} gpmppi_gp;
+
+/* Circular obstacles (Sec. III-C: obstacles are approximated by circles). */
+typedef struct {
+    int32_t n;                  /* 0 <= n <= 4096 */
+    const double *xyr;          /* [n][3] (centre x, centre y, radius > 0), host; may be NULL if n == 0 */
+} gpmppi_obstacles;
+
+/* Lane centreline (Eq. 13): kind 0 = circle (cx, cy, R), kind 1 = closed
+ * polyline through P vertices (the last vertex joins the first). */
+typedef struct {
+    int32_t kind;
+    double cx, cy, R;           /* kind 0 */
+    int32_t P;                  /* kind 1: 3 <= P <= 65536 */
+    const double *pts;          /* kind 1: [P][2] host array */
+    double half_width;          /* r in Eq. (13), > 0 */
+} gpmppi_path;
+
+/* Controller parameters (Alg. 1 inputs; Eqs. 8, 11, 12, 16). */
+typedef struct {
+    int32_t K;                  /* samples, >= 1 */
+    int32_t T;                  /* horizon steps, 1 <= T <= 4096 */
+    double dt;                  /* step length [s] */
+    double tau_v, tau_w;        /* first-order lags of the nominal velocity model */
+    double sig_v, sig_w;        /* Sigma_sim = diag(sig_v^2, sig_w^2), >= 0 */
+    double u_min[2], u_max[2];  /* control box (Eq. 8), u_min < u_max */
+    double lambda;              /* MPPI temperature, > 0 */
+    double p_x;                 /* chance-constraint level (Eq. 7), 0 < p_x < 1 */
+    double w_var, w_dev, w_lane, w_speed, w_obs;   /* stage-cost weights */
+    double v_des;               /* desired speed of the speed term */
+    double discount;            /* lane-exit discount base (0.9 in Eq. 11) */
+    int32_t precision;          /* gpmppi_precision */
+    int32_t problem_id;         /* Philox counter word 2 */
+} gpmppi_params;
+
+/* Optional per-step outputs of a rollout, all SoA with the sample index
+ * innermost.  Any pointer may be NULL (not written). */
+typedef struct {
+    float *x_d;                 /* [T+1][5][K] states (X, Y, theta, v, w), step 0 = x0 */
+    float *sxy_d;               /* [T+1][3][K] (Sigma_XX, Sigma_XY, Sigma_YY) */
+    float *gp_mean_d;           /* [T][2][K] GP means (v, w) of query k */
+    float *gp_var_d;            /* [T][2][K] predictive GP variances */
+    float *d_lane_d;            /* [T][K] distance to the centreline at step k+1 */
+    float *lane_margin_d;       /* [T][K] r_bar - d_lane (lane exit iff < 0), Eq. (14) */
+    float *obs_margin_d;        /* [T][K] min_j d_bar_j (collision iff <= 0; +inf without obstacles), Eq. (16) */
+    float *u_d;                 /* [T][2][K] sampled, clipped controls */
+} gpmppi_trace;
+
+/* Creates a context on the current HIP device.  Copies every host array,
+ * builds both GPs on the GPU in FP64 (Cholesky of K(Z,Z) + sn^2 I, alpha,
+ * W = L^-1; Rasmussen & Williams Alg. 2.1) and packs them for the rollout.
+ * Synchronises the device.  *out is set only on success. */
+gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2],
+                          const gpmppi_obstacles *obstacles, const gpmppi_path *path,
+                          gpmppi_ctx **out);
+
+/* Rebuilds both GPs (same M as at init) - once per GP update, off the hot path.  Synchronises. */
+gpmppi_status gpmppi_set_gp(gpmppi_ctx *ctx, const gpmppi_gp gp[2]);
+
+/* One MPPI iteration (Alg. 1, Step 1): rollout of K samples over T steps
+ * from x0, then weights w^s = exp(-(S^s - min S)/lambda) / sum and
+ * U'_k = sum_s w^s clip(U_k + eps_k^s).
+ *   x0_d      [5] device, initial state
+ *   U_d       [T][2] device, nominal controls
+ *   seed      64-bit Philox key of the control noise (counter (k, s, problem_id, 0))
+ *   U_out_d   [T][2] device, new controls; may alias U_d
+ *   costs_d   [K] device, per-sample costs S^s
+ *   weights_d [K] device, per-sample weights (may be NULL) */
+gpmppi_status gpmppi_step(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed,
+                          float *U_out_d, float *costs_d, float *weights_d, void *stream);
+
+/* The rollout alone (noise, GP, dynamics, covariance, constraints,
+ * costs), optionally writing the per-step trace.  trace may be NULL. */
+gpmppi_status gpmppi_rollout(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed,
+                             float *costs_d, const gpmppi_trace *trace, void *stream);
+
+/* The weighting and control update alone for given costs:
+ * regenerates the sampled controls from (U_d, seed).  U_out_d may alias U_d. */
+gpmppi_status gpmppi_weights_update(gpmppi_ctx *ctx, const float *costs_d, const float *U_d,
+                                    uint64_t seed, float *U_out_d, float *weights_d, void *stream);
+
+/* Evaluates both GPs at n query points q = (v, w, v_cmd, w_cmd), with the same
+ * device arithmetic and precision form as the rollout (Eq. 3, one terrain).
+ *   q_d [n][4] device; mean_d [2][n], var_d [2][n] device (predictive variance). */
+gpmppi_status gpmppi_gp_predict(gpmppi_ctx *ctx, const float *q_d, int32_t n,
+                                float *mean_d, float *var_d, void *stream);
+
+/* Closed loop (the receding-horizon loop of Alg. 1): applies U_d[0] to the synthetic
+ * plant x+ = Euler(x, u) + dt * amplitude * sin(v w) on (v, w), writing x_out_d
+ * (may alias x_d), and shifts U_d in place to [U_1 .. U_{T-1}, U_{T-1}]. */
+gpmppi_status gpmppi_plant_shift(gpmppi_ctx *ctx, const float *x_d, float *x_out_d, float *U_d,
+                                 double amplitude, void *stream);
+
+/* n control steps of the closed loop, all on device: for t < n,
+ * step(x, U, seed0 + t) -> U', plant(U'_0), shift.  x_d [5] and U_d [T][2] are
+ * updated in place; x_hist_d [n+1][5] (may be NULL) receives the states, and
+ * U0_hist_d [n][2] (may be NULL) the applied controls.  use_graph != 0
+ * captures one control step in a HIP graph and replays it n times. */
+gpmppi_status gpmppi_closed_loop(gpmppi_ctx *ctx, float *x_d, float *U_d, uint64_t seed0, int32_t n,
+                                 double amplitude, float *x_hist_d, float *U0_hist_d,
+                                 int32_t use_graph, void *stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) raw output for n counters:
+ * ctr_d [n][4] device (words), out_d [n][4] device; key = (seed lo, seed hi). */
+gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uint32_t *out_d,
+                            void *stream);
+
+/* Reads and clears the context's device status bits (bit 0: a non-finite
+ * cost was seen by a weights/update call).  Synchronises the device. */
+gpmppi_status gpmppi_status_flags(gpmppi_ctx *ctx, uint32_t *flags);
+
+/* Derived scalars of a context: M_pad (M rounded up to the tile size),
+ * z = Phi^-1(p_x) (Eq. 16) and c = sqrt(chi2_2(p_x)) (Eq. 14). */
+gpmppi_status gpmppi_info(const gpmppi_ctx *ctx, int32_t *M_pad, double *z_p, double *c_p);
+
+/* Phi^-1(p), the standard normal quantile used to tighten obstacle margins
+ * (Eq. 16); host-only, needs no device.  Returns NaN outside (0, 1). */
+double gpmppi_norm_quantile(double p);
+
+/* Frees every device buffer of the context (NULL is accepted). */
+void gpmppi_destroy(gpmppi_ctx *ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *gpmppi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPMPPI_H */

@@ -1,0 +1,83 @@
+// Device helpers shared by the gfx950 kernels of the GP-MPPI library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpmppi {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kSamplesPerBlock = 32;   // samples per workgroup (one MFMA column block)
+constexpr int kThreads = 256;          // 4 wave64s
+constexpr int kWaves = kThreads / 64;
+constexpr int kLanesPerSample = kThreads / kSamplesPerBlock;   // 8
+constexpr int kTile = 32;              // rows of W per MFMA tile
+constexpr int kMaxM = 1024;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies whose high halves are mixed with the other words and the key;
+// the key advances by two Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+        const uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// Open-interval uniform ((w >> 9) + 1/2) 2^-23: a multiple of 2^-24 below 1,
+// hence exact in binary32.
+__device__ __forceinline__ float uniform_open(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// Clipped sampled control u = clip(U_k + eps) for step k of sample s
+// (Alg. 1 Step 1 noise with Box-Muller normals; Eq. 8 box).
+struct NoiseParams {
+    uint32_t key0, key1;
+    uint32_t pid;
+    float sig_v, sig_w;
+    float umin0, umin1, umax0, umax1;
+};
+
+__device__ __forceinline__ float2 sampled_control(const NoiseParams &np, int k, int s, float U0,
+                                                  float U1) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)s, np.pid, 0u), np.key0, np.key1);
+    const float u1 = uniform_open(w.x), u2 = uniform_open(w.y);
+    const float r = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    const float a = fminf(fmaxf(U0 + np.sig_v * (r * cs), np.umin0), np.umax0);
+    const float b = fminf(fmaxf(U1 + np.sig_w * (r * sn), np.umin1), np.umax1);
+    return make_float2(a, b);
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __host__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t b;
+    __builtin_memcpy(&b, &x, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ __host__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    const uint32_t b = (uint32_t)h << 16;
+    float x;
+    __builtin_memcpy(&x, &b, 4);
+    return x;
+}
+
+// Wave-level helpers (wave64).
+__device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, 64); }
+
+}  // namespace gpmppi

@@ -1,0 +1,251 @@
+// Once-per-GP-update build of each residual GP in FP64 on the GPU
+// (Rasmussen & Williams Alg. 2.1 with the explicit inverse factor):
+//   A = K(Z, Z) + sn^2 I         SE-ARD covariance (Sec. III-A, Sec. IV-A)
+//   L = chol(A)                  blocked left-looking Cholesky, 32x32 tiles
+//   W = L^-1                     block-column forward substitution
+//   alpha = W^T (W y) = A^-1 y
+// and the packing of W, alpha and the scaled inputs into the FP32 / BF16
+// layouts the rollout streams.  Padding rows/columns (M <= i < Mpad) carry
+// the identity in A and are zeroed when packing.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace gpmppi {
+
+constexpr int NB = 32;   // tile edge
+
+__global__ void kmat_kernel(const double *Z, int M, int Mpad, double i0, double i1, double i2, double i3,
+                            double sf2, double sn2, double *A) {
+    const int j = blockIdx.x * 16 + threadIdx.x;
+    const int i = blockIdx.y * 16 + threadIdx.y;
+    if (i >= Mpad || j >= Mpad) return;
+    double v;
+    if (i < M && j < M) {
+        const double d0 = Z[4 * i] - Z[4 * j], d1 = Z[4 * i + 1] - Z[4 * j + 1];
+        const double d2 = Z[4 * i + 2] - Z[4 * j + 2], d3 = Z[4 * i + 3] - Z[4 * j + 3];
+        const double r2 = d0 * d0 * i0 + d1 * d1 * i1 + d2 * d2 * i2 + d3 * d3 * i3;
+        v = sf2 * exp(-0.5 * r2) + (i == j ? sn2 : 0.0);
+    } else {
+        v = (i == j) ? 1.0 : 0.0;
+    }
+    A[(size_t)i * Mpad + j] = v;
+}
+
+// Left-looking update of block column kb: A[ib][kb] -= sum_{pb<kb} L[ib][pb] L[kb][pb]^T
+// for ib = kb + blockIdx.x; the diagonal block is then factored in place.
+__global__ __launch_bounds__(256) void chol_column_kernel(double *A, int Mpad, int kb, uint32_t *flag) {
+    __shared__ double Ta[NB][NB + 1], Tb[NB][NB + 1], C[NB][NB + 1];
+    const int ib = kb + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int row = tid >> 3, c0 = (tid & 7) * 4;   // each thread: 1 row x 4 columns
+    double acc[4];
+    for (int e = 0; e < 4; ++e) acc[e] = A[(size_t)(ib * NB + row) * Mpad + kb * NB + c0 + e];
+    for (int pb = 0; pb < kb; ++pb) {
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int rr = e / NB, cc = e % NB;
+            Ta[rr][cc] = A[(size_t)(ib * NB + rr) * Mpad + pb * NB + cc];
+            Tb[rr][cc] = A[(size_t)(kb * NB + rr) * Mpad + pb * NB + cc];
+        }
+        __syncthreads();
+        for (int p = 0; p < NB; ++p) {
+            const double a = Ta[row][p];
+            for (int e = 0; e < 4; ++e) acc[e] -= a * Tb[c0 + e][p];
+        }
+        __syncthreads();
+    }
+    if (ib != kb) {
+        for (int e = 0; e < 4; ++e) A[(size_t)(ib * NB + row) * Mpad + kb * NB + c0 + e] = acc[e];
+        return;
+    }
+    for (int e = 0; e < 4; ++e) C[row][c0 + e] = acc[e];
+    __syncthreads();
+    for (int c = 0; c < NB; ++c) {
+        if (tid == 0) {
+            const double d = C[c][c];
+            if (!(d > 0.0)) atomicOr(flag, 1u);
+            C[c][c] = sqrt(d > 0.0 ? d : 1.0);
+        }
+        __syncthreads();
+        if (tid > c && tid < NB) C[tid][c] /= C[c][c];
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e / NB, j = e % NB;
+            if (j > c && i >= j) C[i][j] -= C[i][c] * C[j][c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int i = e / NB, j = e % NB;
+        A[(size_t)(kb * NB + i) * Mpad + kb * NB + j] = (j <= i) ? C[i][j] : 0.0;
+    }
+}
+
+// L[ib][kb] = A[ib][kb] L[kb][kb]^-T for ib = kb + 1 + blockIdx.x.
+__global__ __launch_bounds__(64) void chol_trsm_kernel(double *A, int Mpad, int kb) {
+    __shared__ double Ld[NB][NB + 1], X[NB][NB + 1];
+    const int ib = kb + 1 + blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 64) {
+        const int i = e / NB, j = e % NB;
+        Ld[i][j] = A[(size_t)(kb * NB + i) * Mpad + kb * NB + j];
+        X[i][j] = A[(size_t)(ib * NB + i) * Mpad + kb * NB + j];
+    }
+    __syncthreads();
+    if (tid < NB) {
+        const int rr = tid;   // row of X: X[r][c] = (A[r][c] - sum_{p<c} X[r][p] L[c][p]) / L[c][c]
+        for (int c = 0; c < NB; ++c) {
+            double v = X[rr][c];
+            for (int p = 0; p < c; ++p) v -= X[rr][p] * Ld[c][p];
+            X[rr][c] = v / Ld[c][c];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 64) {
+        const int i = e / NB, j = e % NB;
+        A[(size_t)(ib * NB + i) * Mpad + kb * NB + j] = X[i][j];
+    }
+}
+
+// W[:, jb] = L^-1 e_jb by forward substitution over row blocks ib >= jb;
+// block jb = blockIdx.x.  W is lower triangular; blocks above are zeroed.
+__global__ __launch_bounds__(256) void trinv_kernel(const double *L, double *W, int Mpad) {
+    __shared__ double Lt[NB][NB + 1], Xt[NB][NB + 1], R[NB][NB + 1];
+    const int jb = blockIdx.x, nb = Mpad / NB;
+    const int tid = threadIdx.x;
+    const int row = tid >> 3, c0 = (tid & 7) * 4;
+    for (int ib = 0; ib < jb; ++ib)
+        for (int e = tid; e < NB * NB; e += 256)
+            W[(size_t)(ib * NB + e / NB) * Mpad + jb * NB + e % NB] = 0.0;
+    for (int ib = jb; ib < nb; ++ib) {
+        double acc[4];
+        for (int e = 0; e < 4; ++e) acc[e] = (ib == jb && row == c0 + e) ? 1.0 : 0.0;
+        for (int kb = jb; kb < ib; ++kb) {
+            for (int e = tid; e < NB * NB; e += 256) {
+                const int i = e / NB, j = e % NB;
+                Lt[i][j] = L[(size_t)(ib * NB + i) * Mpad + kb * NB + j];
+                Xt[i][j] = W[(size_t)(kb * NB + i) * Mpad + jb * NB + j];
+            }
+            __syncthreads();
+            for (int p = 0; p < NB; ++p) {
+                const double a = Lt[row][p];
+                for (int e = 0; e < 4; ++e) acc[e] -= a * Xt[p][c0 + e];
+            }
+            __syncthreads();
+        }
+        for (int e = 0; e < 4; ++e) R[row][c0 + e] = acc[e];
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e / NB, j = e % NB;
+            Lt[i][j] = L[(size_t)(ib * NB + i) * Mpad + ib * NB + j];
+        }
+        __syncthreads();
+        if (tid < NB) {   // column tid: solve Lt x = R[:, tid]
+            const int c = tid;
+            for (int i = 0; i < NB; ++i) {
+                double v = R[i][c];
+                for (int p = 0; p < i; ++p) v -= Lt[i][p] * R[p][c];
+                R[i][c] = v / Lt[i][i];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e / NB, j = e % NB;
+            W[(size_t)(ib * NB + i) * Mpad + jb * NB + j] = R[i][j];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void matvec_lower_kernel(const double *W, const double *x, double *y, int Mpad, int transpose) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Mpad) return;
+    double acc = 0.0;
+    if (!transpose) {
+        for (int j = 0; j <= i; ++j) acc += W[(size_t)i * Mpad + j] * x[j];
+    } else {
+        for (int j = i; j < Mpad; ++j) acc += W[(size_t)j * Mpad + i] * x[j];
+    }
+    y[i] = acc;
+}
+
+hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double ell[4], double sf2,
+                           double sn2, hipStream_t st) {
+    const int nb = Mpad / NB;
+    hipLaunchKernelGGL(kmat_kernel, dim3(Mpad / 16, Mpad / 16), dim3(16, 16), 0, st, b.Z, M, Mpad,
+                       1.0 / (ell[0] * ell[0]), 1.0 / (ell[1] * ell[1]), 1.0 / (ell[2] * ell[2]),
+                       1.0 / (ell[3] * ell[3]), sf2, sn2, b.A);
+    for (int kb = 0; kb < nb; ++kb) {
+        hipLaunchKernelGGL(chol_column_kernel, dim3(nb - kb), dim3(256), 0, st, b.A, Mpad, kb, b.flag);
+        if (kb + 1 < nb) hipLaunchKernelGGL(chol_trsm_kernel, dim3(nb - kb - 1), dim3(64), 0, st, b.A, Mpad, kb);
+    }
+    hipLaunchKernelGGL(trinv_kernel, dim3(nb), dim3(256), 0, st, b.A, b.W, Mpad);
+    hipLaunchKernelGGL(matvec_lower_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.W, b.y, b.u, Mpad, 0);
+    hipLaunchKernelGGL(matvec_lower_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.W, b.u, b.alpha, Mpad, 1);
+    return hipGetLastError();
+}
+
+// Packs block (t, jt <= t) of W for lane l (see the layout in rollout.hip).
+__global__ void pack_w_kernel(const double *W, int M, int Mpad, float4 *w32, uint4 *wbh, uint4 *wbl) {
+    const int blk = blockIdx.x, lane = threadIdx.x;
+    int t = 0;
+    while ((t + 1) * (t + 2) / 2 <= blk) ++t;
+    const int jt = blk - t * (t + 1) / 2;
+    const int i = 32 * t + (lane & 31);
+    const int half = lane >> 5;
+    auto wval = [&](int j) -> float {
+        return (i < M && j < M && j <= i) ? (float)W[(size_t)i * Mpad + j] : 0.0f;
+    };
+    for (int q = 0; q < 4; ++q) {
+        float4 v;
+        v.x = wval(32 * jt + 2 * (4 * q + 0) + half);
+        v.y = wval(32 * jt + 2 * (4 * q + 1) + half);
+        v.z = wval(32 * jt + 2 * (4 * q + 2) + half);
+        v.w = wval(32 * jt + 2 * (4 * q + 3) + half);
+        w32[(size_t)blk * 256 + q * 64 + lane] = v;
+    }
+    for (int h = 0; h < 2; ++h) {
+        uint16_t hi[8], lo[8];
+        for (int e = 0; e < 8; ++e) {
+            const float x = wval(32 * jt + 16 * h + 8 * half + e);
+            hi[e] = bf16_rne(x);
+            lo[e] = bf16_rne(x - bf16_to_f32(hi[e]));
+        }
+        uint4 H, Lo;
+        H.x = hi[0] | ((uint32_t)hi[1] << 16);
+        H.y = hi[2] | ((uint32_t)hi[3] << 16);
+        H.z = hi[4] | ((uint32_t)hi[5] << 16);
+        H.w = hi[6] | ((uint32_t)hi[7] << 16);
+        Lo.x = lo[0] | ((uint32_t)lo[1] << 16);
+        Lo.y = lo[2] | ((uint32_t)lo[3] << 16);
+        Lo.z = lo[4] | ((uint32_t)lo[5] << 16);
+        Lo.w = lo[6] | ((uint32_t)lo[7] << 16);
+        wbh[(size_t)blk * 128 + h * 64 + lane] = H;
+        wbl[(size_t)blk * 128 + h * 64 + lane] = Lo;
+    }
+}
+
+__global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int Mpad, double s0, double s1,
+                                double s2, double s3, float *zs, float *al) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Mpad) return;
+    if (j < M) {
+        zs[4 * j] = (float)(Z[4 * j] * s0);
+        zs[4 * j + 1] = (float)(Z[4 * j + 1] * s1);
+        zs[4 * j + 2] = (float)(Z[4 * j + 2] * s2);
+        zs[4 * j + 3] = (float)(Z[4 * j + 3] * s3);
+        al[j] = (float)alpha[j];
+    } else {
+        zs[4 * j] = zs[4 * j + 1] = zs[4 * j + 2] = zs[4 * j + 3] = 0.0f;
+        al[j] = 0.0f;
+    }
+}
+
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], float *zs,
+                          float *alpha, float4 *w32, uint4 *wbh, uint4 *wbl, hipStream_t st) {
+    const int NT = Mpad / 32;
+    hipLaunchKernelGGL(pack_w_kernel, dim3(NT * (NT + 1) / 2), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
+    hipLaunchKernelGGL(pack_vec_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.Z, b.alpha, M, Mpad,
+                       scale[0], scale[1], scale[2], scale[3], zs, alpha);
+    return hipGetLastError();
+}
+
+}  // namespace gpmppi

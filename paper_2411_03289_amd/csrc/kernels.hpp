@@ -1,0 +1,108 @@
+// Kernel argument blocks and host-side launchers of the GP-MPPI library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gpmppi.h"
+#include "device_common.hpp"
+
+namespace gpmppi {
+
+// Device image of the two residual GPs, packed for the rollout.
+//  zs     [2][Mpad][4]  inputs scaled by s_od = sqrt(log2(e)/2) / ell_od, so that
+//                       k = exp2(c2_o - |q s_o - zs|^2) = sf_o^2 exp(-r^2/2)
+//  alpha  [2][Mpad]     (K + sn^2 I)^-1 y, zero beyond M
+//  w32    packed FP32 blocks of W = L^-1 (see pack layout in gp_build.hip)
+//  wbh/wbl packed BF16 hi / lo splits of the same blocks
+struct GpDev {
+    const float *zs;
+    const float *alpha;
+    const float4 *w32;
+    const uint4 *wbh;
+    const uint4 *wbl;
+    long long w32_stride;   // float4 per output
+    long long wb_stride;    // uint4 per output
+    float scale[2][4];
+    float c2[2];
+    float sf2[2];
+    float sn2[2];
+    int Mpad;
+    int NT;                 // Mpad / 32
+};
+
+struct Geometry {
+    int path_kind;          // 0 circle, 1 polyline
+    float cx, cy, R;
+    int P;
+    const float4 *seg;      // [P] (ax, ay, ex, ey), e = b - a
+    const float *seg_inv;   // [P] 1 / |e|^2
+    float half_width, inv_half_width;
+    int n_obs;
+    const float4 *obs;      // [n_obs] (cx, cy, r, 0)
+    float z_p, c_p;         // Phi^-1(p_x), sqrt(chi2_2(p_x))
+};
+
+struct CostWeights {
+    float w_var, w_dev, w_lane, w_speed, w_obs, v_des, discount;
+};
+
+struct Dyn {
+    float dt, dt_tau_v, dt_tau_w;   // dt, dt/tau_v, dt/tau_w
+    float a33, a44;                 // 1 - dt/tau_v, 1 - dt/tau_w
+};
+
+struct RolloutArgs {
+    GpDev gp;
+    Geometry geo;
+    CostWeights cw;
+    Dyn dyn;
+    NoiseParams noise;              // key words are the base seed's
+    uint64_t seed;
+    const uint32_t *step_counter;   // if non-NULL, seed + *step_counter keys the noise
+    int K, T;
+    const float *x0;                // [5]
+    const float *U;                 // [T][2]
+    float *costs;                   // [K]
+    gpmppi_trace trace;
+};
+
+struct UpdateArgs {
+    NoiseParams noise;
+    uint64_t seed;
+    const uint32_t *step_counter;
+    int K, T;
+    float lambda;
+    const float *costs;
+    const float *U;
+    float *U_out;
+    float *weights;
+    uint32_t *flags;
+};
+
+size_t rollout_lds_bytes(int precision, int Mpad);
+hipError_t launch_rollout(const RolloutArgs &a, int precision, hipStream_t st);
+hipError_t launch_gp_predict(const GpDev &g, int precision, const float *q, int n, float *mean,
+                             float *var, hipStream_t st);
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
+hipError_t launch_philox(uint64_t seed, const uint32_t *ctr, int n, uint32_t *out, hipStream_t st);
+hipError_t launch_plant_shift(const float *x, float *x_out, float *U, int T, Dyn dyn, float amplitude,
+                              uint32_t *step_counter, float *x_hist, float *U0_hist, hipStream_t st);
+hipError_t launch_counter_reset(uint32_t *counter, hipStream_t st);
+
+// FP64 GP build on the device (per output).
+struct GpBuildBuffers {
+    double *A;        // [Mpad][Mpad] K + sn^2 I, overwritten by L (lower)
+    double *W;        // [Mpad][Mpad] L^-1
+    double *Z;        // [M][4]
+    double *y;        // [Mpad]
+    double *u;        // [Mpad] scratch
+    double *alpha;    // [Mpad]
+    uint32_t *flag;   // non-PD flag
+};
+hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double ell[4], double sf2,
+                           double sn2, hipStream_t st);
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], float *zs,
+                          float *alpha, float4 *w32, uint4 *wbh, uint4 *wbl, hipStream_t st);
+
+}  // namespace gpmppi

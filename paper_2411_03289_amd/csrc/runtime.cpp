@@ -1,0 +1,522 @@
+// Host runtime of the GP-MPPI library: argument validation, context and
+// device buffers, GP build orchestration, kernel launches and the closed loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using namespace gpmppi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gpmppi_status fail(gpmppi_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(GPMPPI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+// Phi^-1(p): the upper-tail probability q = min(p, 1-p) is inverted by
+// bisection on 0.5 erfc(z / sqrt 2) = q over [0, 40], refined by Newton steps.
+double norm_quantile(double p) {
+    const double q = p < 0.5 ? p : 1.0 - p;
+    auto tail = [](double z) { return 0.5 * std::erfc(z / std::sqrt(2.0)); };
+    double lo = 0.0, hi = 40.0;
+    for (int i = 0; i < 200; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        if (tail(mid) > q) lo = mid; else hi = mid;
+    }
+    double z = 0.5 * (lo + hi);
+    for (int i = 0; i < 3; ++i) {
+        const double phi = std::exp(-0.5 * z * z) / std::sqrt(2.0 * M_PI);
+        if (phi > 0) z += (tail(z) - q) / phi;
+    }
+    return p < 0.5 ? -z : z;
+}
+
+template <typename T>
+T *dev_alloc(size_t n, gpmppi_status &st) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+        st = fail(GPMPPI_E_NOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        return nullptr;
+    }
+    return static_cast<T *>(p);
+}
+
+}  // namespace
+
+struct gpmppi_ctx {
+    int device = 0;
+    gpmppi_params params{};
+    int M = 0, Mpad = 0, NT = 0;
+    double z_p = 0, c_p = 0;
+    // device buffers
+    float *zs = nullptr, *alpha = nullptr;
+    float4 *w32 = nullptr;
+    uint4 *wbh = nullptr, *wbl = nullptr;
+    long long w32_stride = 0, wb_stride = 0;
+    float4 *obs = nullptr;
+    float4 *seg = nullptr;
+    float *seg_inv = nullptr;
+    uint32_t *flags = nullptr;       // [0] status bits, [1] non-PD flag, [2] closed-loop step counter
+    double *A64 = nullptr, *W64 = nullptr, *Z64 = nullptr, *y64 = nullptr, *u64 = nullptr, *al64 = nullptr;
+    float *U_scratch = nullptr;      // [T][2] new controls inside the closed loop
+    float *cost_scratch = nullptr;   // [K]
+    // host copies
+    GpDev gp{};
+    Geometry geo{};
+    CostWeights cw{};
+    Dyn dyn{};
+    int n_obs = 0;
+    std::vector<void *> owned;
+
+    ~gpmppi_ctx() {
+        for (void *p : owned) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+gpmppi_status validate_params(const gpmppi_params *p) {
+    if (!p) return fail(GPMPPI_E_INVALID, "params is NULL");
+    if (p->K < 1) return fail(GPMPPI_E_INVALID, "K must be >= 1 (got %d)", p->K);
+    if (p->K > (1 << 24)) return fail(GPMPPI_E_UNSUPPORTED, "K must be <= 2^24 (got %d)", p->K);
+    if (p->T < 1 || p->T > 4096) return fail(GPMPPI_E_INVALID, "T must lie in [1, 4096] (got %d)", p->T);
+    const double vals[] = {p->dt, p->tau_v, p->tau_w, p->sig_v, p->sig_w, p->u_min[0], p->u_min[1],
+                           p->u_max[0], p->u_max[1], p->lambda, p->p_x, p->w_var, p->w_dev, p->w_lane,
+                           p->w_speed, p->w_obs, p->v_des, p->discount};
+    for (double v : vals)
+        if (!is_fin(v)) return fail(GPMPPI_E_NONFINITE, "non-finite controller parameter");
+    if (!(p->dt > 0) || !(p->tau_v > 0) || !(p->tau_w > 0))
+        return fail(GPMPPI_E_INVALID, "dt, tau_v and tau_w must be > 0");
+    if (p->sig_v < 0 || p->sig_w < 0) return fail(GPMPPI_E_INVALID, "noise scales must be >= 0");
+    if (!(p->u_min[0] < p->u_max[0]) || !(p->u_min[1] < p->u_max[1]))
+        return fail(GPMPPI_E_INVALID, "u_min must be < u_max");
+    if (!(p->lambda > 0)) return fail(GPMPPI_E_INVALID, "lambda must be > 0");
+    if (!(p->p_x > 0 && p->p_x < 1)) return fail(GPMPPI_E_INVALID, "p_x must lie in (0, 1)");
+    if (p->precision < 0 || p->precision > 2) return fail(GPMPPI_E_INVALID, "unknown precision %d", p->precision);
+    if (p->problem_id < 0) return fail(GPMPPI_E_INVALID, "problem_id must be >= 0");
+    return GPMPPI_OK;
+}
+
+gpmppi_status validate_gp(const gpmppi_gp gp[2]) {
+    if (!gp) return fail(GPMPPI_E_INVALID, "gp is NULL");
+    if (gp[0].M != gp[1].M) return fail(GPMPPI_E_INVALID, "both GPs must have the same M");
+    for (int o = 0; o < 2; ++o) {
+        const gpmppi_gp &g = gp[o];
+        if (g.M < 1) return fail(GPMPPI_E_INVALID, "GP %d: M must be >= 1", o);
+        if (g.M > kMaxM) return fail(GPMPPI_E_UNSUPPORTED, "GP %d: M = %d exceeds %d", o, g.M, kMaxM);
+        if (!g.Z || !g.y) return fail(GPMPPI_E_INVALID, "GP %d: Z or y is NULL", o);
+        for (int i = 0; i < 4 * g.M; ++i)
+            if (!is_fin(g.Z[i])) return fail(GPMPPI_E_NONFINITE, "GP %d: non-finite input Z", o);
+        for (int i = 0; i < g.M; ++i)
+            if (!is_fin(g.y[i])) return fail(GPMPPI_E_NONFINITE, "GP %d: non-finite target y", o);
+        for (int d = 0; d < 4; ++d)
+            if (!is_fin(g.log_ell[d]) || std::fabs(g.log_ell[d]) > 30)
+                return fail(GPMPPI_E_INVALID, "GP %d: log lengthscale out of range", o);
+        if (!is_fin(g.log_sf) || std::fabs(g.log_sf) > 30 || !is_fin(g.log_sn) || std::fabs(g.log_sn) > 30)
+            return fail(GPMPPI_E_INVALID, "GP %d: log sigma out of range", o);
+    }
+    return GPMPPI_OK;
+}
+
+gpmppi_status validate_world(const gpmppi_obstacles *ob, const gpmppi_path *pa) {
+    if (!ob || !pa) return fail(GPMPPI_E_INVALID, "obstacles or path is NULL");
+    if (ob->n < 0 || ob->n > 4096) return fail(GPMPPI_E_INVALID, "obstacle count must lie in [0, 4096]");
+    if (ob->n > 0 && !ob->xyr) return fail(GPMPPI_E_INVALID, "obstacle array is NULL");
+    for (int j = 0; j < ob->n; ++j) {
+        for (int c = 0; c < 3; ++c)
+            if (!is_fin(ob->xyr[3 * j + c])) return fail(GPMPPI_E_NONFINITE, "non-finite obstacle");
+        if (!(ob->xyr[3 * j + 2] > 0)) return fail(GPMPPI_E_INVALID, "obstacle radius must be > 0");
+    }
+    if (!is_fin(pa->half_width) || !(pa->half_width > 0))
+        return fail(GPMPPI_E_INVALID, "lane half-width must be > 0");
+    if (pa->kind == 0) {
+        if (!is_fin(pa->cx) || !is_fin(pa->cy) || !is_fin(pa->R) || !(pa->R > 0))
+            return fail(GPMPPI_E_INVALID, "circle path needs finite centre and R > 0");
+    } else if (pa->kind == 1) {
+        if (pa->P < 3 || pa->P > 65536 || !pa->pts) return fail(GPMPPI_E_INVALID, "polyline needs 3..65536 vertices");
+        for (int i = 0; i < 2 * pa->P; ++i)
+            if (!is_fin(pa->pts[i])) return fail(GPMPPI_E_NONFINITE, "non-finite path vertex");
+        for (int i = 0; i < pa->P; ++i) {
+            const int n = (i + 1) % pa->P;
+            if (pa->pts[2 * i] == pa->pts[2 * n] && pa->pts[2 * i + 1] == pa->pts[2 * n + 1])
+                return fail(GPMPPI_E_INVALID, "polyline has a zero-length segment at vertex %d", i);
+        }
+    } else {
+        return fail(GPMPPI_E_INVALID, "unknown path kind %d", pa->kind);
+    }
+    return GPMPPI_OK;
+}
+
+gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
+    const int M = c->M, Mpad = c->Mpad;
+    const double kScale = std::sqrt(0.5 / std::log(2.0));   // sqrt(log2(e) / 2)
+    for (int o = 0; o < 2; ++o) {
+        std::vector<double> y(Mpad, 0.0);
+        std::memcpy(y.data(), gp[o].y, sizeof(double) * M);
+        HIP_TRY(hipMemcpy(c->Z64, gp[o].Z, sizeof(double) * 4 * M, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->y64, y.data(), sizeof(double) * Mpad, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(c->flags + 1, 0, sizeof(uint32_t)));
+        double ell[4], scale[4];
+        for (int d = 0; d < 4; ++d) {
+            ell[d] = std::exp(gp[o].log_ell[d]);
+            scale[d] = kScale / ell[d];
+        }
+        const double sf2 = std::exp(2.0 * gp[o].log_sf), sn2 = std::exp(2.0 * gp[o].log_sn);
+        GpBuildBuffers b{c->A64, c->W64, c->Z64, c->y64, c->u64, c->al64, c->flags + 1};
+        HIP_TRY(build_gp_output(b, M, Mpad, ell, sf2, sn2, nullptr));
+        uint32_t notpd = 0;
+        HIP_TRY(hipMemcpy(&notpd, c->flags + 1, sizeof notpd, hipMemcpyDeviceToHost));
+        if (notpd) return fail(GPMPPI_E_NOT_PD, "GP %d: K(Z,Z) + sn^2 I is not positive definite", o);
+        HIP_TRY(pack_gp_output(b, M, Mpad, scale, c->zs + (size_t)o * Mpad * 4, c->alpha + (size_t)o * Mpad,
+                               c->w32 + o * c->w32_stride, c->wbh + o * c->wb_stride, c->wbl + o * c->wb_stride,
+                               nullptr));
+        HIP_TRY(hipDeviceSynchronize());
+        for (int d = 0; d < 4; ++d) c->gp.scale[o][d] = (float)scale[d];
+        c->gp.c2[o] = (float)(2.0 * gp[o].log_sf / std::log(2.0));
+        c->gp.sf2[o] = (float)sf2;
+        c->gp.sn2[o] = (float)sn2;
+    }
+    return GPMPPI_OK;
+}
+
+NoiseParams noise_of(const gpmppi_ctx *c) {
+    NoiseParams np{};
+    np.pid = (uint32_t)c->params.problem_id;
+    np.sig_v = (float)c->params.sig_v;
+    np.sig_w = (float)c->params.sig_w;
+    np.umin0 = (float)c->params.u_min[0];
+    np.umin1 = (float)c->params.u_min[1];
+    np.umax0 = (float)c->params.u_max[0];
+    np.umax1 = (float)c->params.u_max[1];
+    return np;
+}
+
+RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, uint64_t seed, float *costs,
+                         const gpmppi_trace *trace, const uint32_t *step_counter) {
+    RolloutArgs a{};
+    a.gp = c->gp;
+    a.geo = c->geo;
+    a.cw = c->cw;
+    a.dyn = c->dyn;
+    a.noise = noise_of(c);
+    a.seed = seed;
+    a.step_counter = step_counter;
+    a.K = c->params.K;
+    a.T = c->params.T;
+    a.x0 = x0;
+    a.U = U;
+    a.costs = costs;
+    if (trace) a.trace = *trace;
+    return a;
+}
+
+UpdateArgs update_args(const gpmppi_ctx *c, const float *costs, const float *U, uint64_t seed, float *U_out,
+                       float *weights, const uint32_t *step_counter) {
+    UpdateArgs u{};
+    u.noise = noise_of(c);
+    u.seed = seed;
+    u.step_counter = step_counter;
+    u.K = c->params.K;
+    u.T = c->params.T;
+    u.lambda = (float)c->params.lambda;
+    u.costs = costs;
+    u.U = U;
+    u.U_out = U_out;
+    u.weights = weights;
+    u.flags = c->flags;
+    return u;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gpmppi_last_error(void) { return g_last_error.c_str(); }
+
+gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], const gpmppi_obstacles *obstacles,
+                          const gpmppi_path *path, gpmppi_ctx **out) {
+    g_last_error.clear();
+    if (!out) return fail(GPMPPI_E_INVALID, "out is NULL");
+    gpmppi_status st;
+    if ((st = validate_params(params)) != GPMPPI_OK) return st;
+    if ((st = validate_gp(gp)) != GPMPPI_OK) return st;
+    if ((st = validate_world(obstacles, path)) != GPMPPI_OK) return st;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GPMPPI_E_HIP, "no HIP device available");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto *c = new gpmppi_ctx();
+    c->device = dev;
+    c->params = *params;
+    c->M = gp[0].M;
+    c->Mpad = (c->M + 31) / 32 * 32;
+    c->NT = c->Mpad / 32;
+    const int Mpad = c->Mpad, NT = c->NT;
+    c->w32_stride = (long long)NT * (NT + 1) / 2 * 256;
+    c->wb_stride = (long long)NT * (NT + 1) / 2 * 128;
+    c->n_obs = obstacles->n;
+    const int P = path->kind == 1 ? path->P : 0;
+
+    st = GPMPPI_OK;
+    auto track = [&](auto *p) {
+        if (p) c->owned.push_back((void *)p);
+        return p;
+    };
+    c->zs = track(dev_alloc<float>((size_t)2 * Mpad * 4, st));
+    c->alpha = track(dev_alloc<float>((size_t)2 * Mpad, st));
+    c->w32 = track(dev_alloc<float4>((size_t)2 * c->w32_stride, st));
+    c->wbh = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
+    c->wbl = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
+    c->obs = track(dev_alloc<float4>((size_t)std::max(1, c->n_obs), st));
+    c->seg = track(dev_alloc<float4>((size_t)std::max(1, P), st));
+    c->seg_inv = track(dev_alloc<float>((size_t)std::max(1, P), st));
+    c->flags = track(dev_alloc<uint32_t>(4, st));
+    c->A64 = track(dev_alloc<double>((size_t)Mpad * Mpad, st));
+    c->W64 = track(dev_alloc<double>((size_t)Mpad * Mpad, st));
+    c->Z64 = track(dev_alloc<double>((size_t)Mpad * 4, st));
+    c->y64 = track(dev_alloc<double>((size_t)Mpad, st));
+    c->u64 = track(dev_alloc<double>((size_t)Mpad, st));
+    c->al64 = track(dev_alloc<double>((size_t)Mpad, st));
+    c->U_scratch = track(dev_alloc<float>((size_t)2 * params->T, st));
+    c->cost_scratch = track(dev_alloc<float>((size_t)params->K, st));
+    if (st != GPMPPI_OK) {
+        delete c;
+        return st;
+    }
+    if (hipMemset(c->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+        delete c;
+        return fail(GPMPPI_E_HIP, "hipMemset failed");
+    }
+
+    // world geometry in FP32
+    std::vector<float4> obs(std::max(1, c->n_obs));
+    for (int j = 0; j < c->n_obs; ++j)
+        obs[j] = make_float4((float)obstacles->xyr[3 * j], (float)obstacles->xyr[3 * j + 1],
+                             (float)obstacles->xyr[3 * j + 2], 0.0f);
+    std::vector<float4> seg(std::max(1, P));
+    std::vector<float> seg_inv(std::max(1, P), 0.0f);
+    for (int i = 0; i < P; ++i) {
+        const int n = (i + 1) % P;
+        const double ax = path->pts[2 * i], ay = path->pts[2 * i + 1];
+        const double ex = path->pts[2 * n] - ax, ey = path->pts[2 * n + 1] - ay;
+        seg[i] = make_float4((float)ax, (float)ay, (float)ex, (float)ey);
+        seg_inv[i] = (float)(1.0 / (ex * ex + ey * ey));
+    }
+    if (hipMemcpy(c->obs, obs.data(), sizeof(float4) * obs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->seg, seg.data(), sizeof(float4) * seg.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->seg_inv, seg_inv.data(), sizeof(float) * seg_inv.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        delete c;
+        return fail(GPMPPI_E_HIP, "upload of the world geometry failed");
+    }
+    c->z_p = norm_quantile(params->p_x);
+    c->c_p = std::sqrt(-2.0 * std::log1p(-params->p_x));
+
+    c->gp.zs = c->zs;
+    c->gp.alpha = c->alpha;
+    c->gp.w32 = c->w32;
+    c->gp.wbh = c->wbh;
+    c->gp.wbl = c->wbl;
+    c->gp.w32_stride = c->w32_stride;
+    c->gp.wb_stride = c->wb_stride;
+    c->gp.Mpad = Mpad;
+    c->gp.NT = NT;
+
+    Geometry &g = c->geo;
+    g.path_kind = path->kind;
+    g.cx = (float)path->cx;
+    g.cy = (float)path->cy;
+    g.R = (float)path->R;
+    g.P = P;
+    g.seg = c->seg;
+    g.seg_inv = c->seg_inv;
+    g.half_width = (float)path->half_width;
+    g.inv_half_width = (float)(1.0 / path->half_width);
+    g.n_obs = c->n_obs;
+    g.obs = c->obs;
+    g.z_p = (float)c->z_p;
+    g.c_p = (float)c->c_p;
+
+    c->cw = CostWeights{(float)params->w_var, (float)params->w_dev, (float)params->w_lane, (float)params->w_speed,
+                        (float)params->w_obs, (float)params->v_des, (float)params->discount};
+    c->dyn = Dyn{(float)params->dt, (float)(params->dt / params->tau_v), (float)(params->dt / params->tau_w),
+                 (float)(1.0 - params->dt / params->tau_v), (float)(1.0 - params->dt / params->tau_w)};
+
+    if ((st = build_gps(c, gp)) != GPMPPI_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_set_gp(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
+    g_last_error.clear();
+    if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
+    gpmppi_status st;
+    if ((st = validate_gp(gp)) != GPMPPI_OK) return st;
+    if (gp[0].M != c->M) return fail(GPMPPI_E_INVALID, "M must stay %d (got %d)", c->M, gp[0].M);
+    return build_gps(c, gp);
+}
+
+gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, float *costs_d,
+                             const gpmppi_trace *trace, void *stream) {
+    g_last_error.clear();
+    if (!c || !x0_d || !U_d || !costs_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    const RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
+    HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_weights_update(gpmppi_ctx *c, const float *costs_d, const float *U_d, uint64_t seed,
+                                    float *U_out_d, float *weights_d, void *stream) {
+    g_last_error.clear();
+    if (!c || !costs_d || !U_d || !U_out_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
+    HIP_TRY(launch_update(u, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_step(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, float *U_out_d,
+                          float *costs_d, float *weights_d, void *stream) {
+    g_last_error.clear();
+    if (!c || !x0_d || !U_d || !U_out_d || !costs_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    const RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
+    HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
+    const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
+    HIP_TRY(launch_update(u, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_gp_predict(gpmppi_ctx *c, const float *q_d, int32_t n, float *mean_d, float *var_d,
+                                void *stream) {
+    g_last_error.clear();
+    if (!c || !q_d || !mean_d || !var_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n < 1) return fail(GPMPPI_E_INVALID, "n must be >= 1");
+    HIP_TRY(launch_gp_predict(c->gp, c->params.precision, q_d, n, mean_d, var_d, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_plant_shift(gpmppi_ctx *c, const float *x_d, float *x_out_d, float *U_d, double amplitude,
+                                 void *stream) {
+    g_last_error.clear();
+    if (!c || !x_d || !x_out_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (!is_fin(amplitude)) return fail(GPMPPI_E_NONFINITE, "non-finite plant amplitude");
+    HIP_TRY(launch_plant_shift(x_d, x_out_d, U_d, c->params.T, c->dyn, (float)amplitude, nullptr, nullptr, nullptr,
+                               (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t seed0, int32_t n,
+                                 double amplitude, float *x_hist_d, float *U0_hist_d, int32_t use_graph,
+                                 void *stream) {
+    g_last_error.clear();
+    if (!c || !x_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n < 0) return fail(GPMPPI_E_INVALID, "n must be >= 0");
+    if (!is_fin(amplitude)) return fail(GPMPPI_E_NONFINITE, "non-finite plant amplitude");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *counter = c->flags + 2;
+    HIP_TRY(launch_counter_reset(counter, st));
+    if (x_hist_d) HIP_TRY(hipMemcpyAsync(x_hist_d, x_d, 5 * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (n == 0) return GPMPPI_OK;
+    // one control step: rollout -> weights/update -> plant + shift, keyed by seed0 + counter
+    auto enqueue = [&](hipStream_t s) -> gpmppi_status {
+        const RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
+        HIP_TRY(launch_rollout(a, c->params.precision, s));
+        const UpdateArgs u = update_args(c, c->cost_scratch, U_d, seed0, U_d, nullptr, counter);
+        HIP_TRY(launch_update(u, s));
+        HIP_TRY(launch_plant_shift(x_d, x_d, U_d, c->params.T, c->dyn, (float)amplitude, counter, x_hist_d,
+                                   U0_hist_d, s));
+        return GPMPPI_OK;
+    };
+    if (!use_graph) {
+        for (int t = 0; t < n; ++t) {
+            gpmppi_status s = enqueue(st);
+            if (s != GPMPPI_OK) return s;
+        }
+        return GPMPPI_OK;
+    }
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipEvent_t ready;
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ready, st));
+    HIP_TRY(hipStreamWaitEvent(cap, ready, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    gpmppi_status s = enqueue(cap);
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (s != GPMPPI_OK) return s;
+    if (ce != hipSuccess) return fail(GPMPPI_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (int t = 0; t < n; ++t) HIP_TRY(hipGraphLaunch(exec, cap));
+    HIP_TRY(hipEventRecord(ready, cap));
+    HIP_TRY(hipStreamWaitEvent(st, ready, 0));
+    HIP_TRY(hipStreamSynchronize(cap));
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ready);
+    (void)hipStreamDestroy(cap);
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uint32_t *out_d, void *stream) {
+    g_last_error.clear();
+    if (!ctr_d || !out_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n < 1) return fail(GPMPPI_E_INVALID, "n must be >= 1");
+    HIP_TRY(launch_philox(seed, ctr_d, n, out_d, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_status_flags(gpmppi_ctx *c, uint32_t *flags) {
+    g_last_error.clear();
+    if (!c || !flags) return fail(GPMPPI_E_INVALID, "NULL argument");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(c->flags, 0, sizeof(uint32_t)));
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_info(const gpmppi_ctx *c, int32_t *M_pad, double *z_p, double *c_p) {
+    g_last_error.clear();
+    if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
+    if (M_pad) *M_pad = c->Mpad;
+    if (z_p) *z_p = c->z_p;
+    if (c_p) *c_p = c->c_p;
+    return GPMPPI_OK;
+}
+
+double gpmppi_norm_quantile(double p) {
+    if (!(p > 0.0 && p < 1.0)) return std::nan("");
+    return norm_quantile(p);
+}
+
+void gpmppi_destroy(gpmppi_ctx *c) { delete c; }
+
+}  // extern "C"
