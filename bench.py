@@ -62,7 +62,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
-    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--cpu-samples", type=int, default=4096)
+    ap.add_argument("--copy-calibrate-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -77,6 +79,15 @@ def main():
     from paper_2411_03289_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibrate_mib:
+        n = args.copy_calibrate_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibrate_mib} MiB done")
+        del src, dst
     pr = W.make_config(2)
     K, T, M = pr.K, pr.T, pr.M
     golden_path = os.path.join(ROOT, "tests", "golden", "c2_oracle.npz")
