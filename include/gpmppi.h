@@ -181,7 +181,7 @@ gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uin
  * cost was seen by a weights/update call).  Synchronises the device. */
 gpmppi_status gpmppi_status_flags(gpmppi_ctx *ctx, uint32_t *flags);
 
-/* Derived scalars of a context: M_pad (M rounded up to the tile size),
+/* Derived scalars of a context: M_pad (M rounded up to a multiple of 64),
  * z = Phi^-1(p_x) (Eq. 16) and c = sqrt(chi2_2(p_x)) (Eq. 14). */
 gpmppi_status gpmppi_info(const gpmppi_ctx *ctx, int32_t *M_pad, double *z_p, double *c_p);
 

@@ -183,12 +183,16 @@ hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const doubl
     return hipGetLastError();
 }
 
-// Packs block (t, jt <= t) of W for lane l (see the layout in rollout.hip).
+// Packs the W blocks in the rollout's pair-major order: block index
+// b = 2 (u (u + 1) + it) + side holds rows of tile t = 2u + side and columns of
+// block column it (it <= 2u + 1); entries above the diagonal or beyond M are 0.
 __global__ void pack_w_kernel(const double *W, int M, int Mpad, float4 *w32, uint4 *wbh, uint4 *wbl) {
     const int blk = blockIdx.x, lane = threadIdx.x;
-    int t = 0;
-    while ((t + 1) * (t + 2) / 2 <= blk) ++t;
-    const int jt = blk - t * (t + 1) / 2;
+    const int side = blk & 1, half_idx = blk >> 1;   // half_idx = u (u + 1) + it
+    int u = 0;
+    while ((u + 1) * (u + 2) <= half_idx) ++u;
+    const int it = half_idx - u * (u + 1);
+    const int t = 2 * u + side;
     const int i = 32 * t + (lane & 31);
     const int half = lane >> 5;
     auto wval = [&](int j) -> float {
@@ -196,16 +200,16 @@ __global__ void pack_w_kernel(const double *W, int M, int Mpad, float4 *w32, uin
     };
     for (int q = 0; q < 4; ++q) {
         float4 v;
-        v.x = wval(32 * jt + 2 * (4 * q + 0) + half);
-        v.y = wval(32 * jt + 2 * (4 * q + 1) + half);
-        v.z = wval(32 * jt + 2 * (4 * q + 2) + half);
-        v.w = wval(32 * jt + 2 * (4 * q + 3) + half);
+        v.x = wval(32 * it + 2 * (4 * q + 0) + half);
+        v.y = wval(32 * it + 2 * (4 * q + 1) + half);
+        v.z = wval(32 * it + 2 * (4 * q + 2) + half);
+        v.w = wval(32 * it + 2 * (4 * q + 3) + half);
         w32[(size_t)blk * 256 + q * 64 + lane] = v;
     }
     for (int h = 0; h < 2; ++h) {
         uint16_t hi[8], lo[8];
         for (int e = 0; e < 8; ++e) {
-            const float x = wval(32 * jt + 16 * h + 8 * half + e);
+            const float x = wval(32 * it + 16 * h + 8 * half + e);
             hi[e] = bf16_rne(x);
             lo[e] = bf16_rne(x - bf16_to_f32(hi[e]));
         }
@@ -241,8 +245,8 @@ __global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int
 
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], float *zs,
                           float *alpha, float4 *w32, uint4 *wbh, uint4 *wbl, hipStream_t st) {
-    const int NT = Mpad / 32;
-    hipLaunchKernelGGL(pack_w_kernel, dim3(NT * (NT + 1) / 2), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
+    const int NP = (Mpad / 32 + 1) / 2;
+    hipLaunchKernelGGL(pack_w_kernel, dim3(2 * NP * (NP + 1)), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
     hipLaunchKernelGGL(pack_vec_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.Z, b.alpha, M, Mpad,
                        scale[0], scale[1], scale[2], scale[3], zs, alpha);
     return hipGetLastError();

@@ -1,20 +1,25 @@
 // K-sample x T-step rollout of the GP-augmented chance-constrained MPPI
 // controller on gfx950 (Alg. 1 Step 1 with Eqs. 1-3, 10, 11-16).
 //
-// Work decomposition: one workgroup of 256 threads (4 wave64s) owns 32
-// samples.  Thread t serves sample s = t / 8 with sub-lane r = t % 8; the 8
-// lanes of a sample hold identical copies of its state x (5) and covariance
-// Sigma (15 symmetric entries) in registers for the whole horizon and split
-// the sample's loops (kernel vector chunks, polyline segments, obstacles).
+// Work decomposition: one workgroup of 256 threads (4 wave64s) owns
+// B = 32 G samples (G = 1 or 2 column groups of the 32x32 matrix-core tiles).
+// Every wave keeps the state x (5) and covariance Sigma (15 symmetric entries)
+// of all B samples in registers for the whole horizon, lane l holding sample
+// l % B; the waves (and, for G = 1, the two half-waves) split the loops over
+// training points, polyline segments and obstacles between them.
 //
 // Per step and per GP output o:
-//  1. kernel vector: k_oj = exp2(c2_o - |q s_o - zs_oj|^2) for the 32 samples
-//     of the block and every training point j (VALU exp), written to LDS in
-//     the matrix-core operand layout; the GP mean k^T alpha is summed in FP32.
+//  1. kernel vector: k_oj = exp2(c2_o - |q s_o - zs_oj|^2) for every sample and
+//     training point (VALU exp), the scaled inputs zs and alpha being read from
+//     LDS as broadcasts; k goes to LDS in the matrix-core operand layout and the
+//     GP mean k^T alpha is summed in FP32.
 //  2. variance: v = W k with W = L^-1 lower triangular, on the matrix cores:
 //     each wave walks its share of the 32x32 blocks (t, jt <= t) of W,
-//     streaming W from L2 through a register ring and reading k from LDS,
-//     and sums |v|^2 per sample; s2 = sn^2 + max(0, sf^2 - |v|^2).
+//     streaming W from L2 through a register ring (distance D) while the k
+//     operand for the next block is read from LDS one block ahead; each W block
+//     serves G sample groups.  s2 = sn^2 + max(0, sf^2 - |v|^2).
+//     Odd steps walk outputs and blocks in reverse order, so that an L2 too
+//     small for both outputs' W still keeps most of it between steps.
 //  3. per-sample Euler step, covariance A Sigma A^T + dt^2 diag(0,0,0,s2),
 //     lane/obstacle tightening and the stage cost.
 #include "device_common.hpp"
@@ -23,12 +28,17 @@
 namespace gpmppi {
 
 // ---------------------------------------------------------------- W blocks
-// Packed block (t, jt) of W (rows 32t.., columns 32jt..), index
-// b = t (t + 1) / 2 + jt, lane l of a wave:
-//   FP32: float4 [b][q][l], component c: W[32t + l%32][32jt + 2(4q+c) + l/32]
-//   BF16: uint4  [b][h][l], element e:   W[32t + l%32][32jt + 16h + 8(l/32) + e]
-// The LDS operand holds k in the same lane order with the sample s = l % 32
-// in place of the W row.
+// W is walked in row-tile pairs (2u, 2u + 1), u < NP = NT / 2 (Mpad is a
+// multiple of 64, so NT = Mpad / 32 is even): pair u
+// takes 2u + 2 iterations it = 0 .. 2u + 1, each holding the two 32x32 blocks
+// (2u, it) and (2u + 1, it) of W (rows 32t.., columns 32 it..).  Block (2u, 2u+1)
+// lies above the diagonal and is stored as zeros, and so is every block of a
+// row tile beyond the matrix, so all iterations are alike.  Packed block index
+// b = 2 (u (u + 1) + it) + side, lane l of a wave:
+//   FP32: float4 [b][q][l], component c: W[32t + l%32][32 it + 2(4q+c) + l/32]
+//   BF16: uint4  [b][h][l], element e:   W[32t + l%32][32 it + 16h + 8(l/32) + e]
+// The LDS operand of sample group g holds k in the same lane order with the
+// sample 32g + l % 32 in place of the W row.
 template <int PREC>
 struct WBlock;
 template <>
@@ -41,6 +51,23 @@ struct WBlock<GPMPPI_BF16> {
 };
 template <>
 struct WBlock<GPMPPI_BF16X3> {
+    uint4 h[2];
+    uint4 l[2];
+};
+
+// k operand of one sample group for one block column.
+template <int PREC>
+struct KOp;
+template <>
+struct KOp<GPMPPI_FP32> {
+    float4 v[4];
+};
+template <>
+struct KOp<GPMPPI_BF16> {
+    uint4 h[2];
+};
+template <>
+struct KOp<GPMPPI_BF16X3> {
     uint4 h[2];
     uint4 l[2];
 };
@@ -65,6 +92,32 @@ __device__ __forceinline__ void load_wblock(WBlock<PREC> &b, const GpDev &g, int
     }
 }
 
+// Byte size of one sample group's k operand in LDS.
+template <int PREC>
+__host__ __device__ constexpr size_t kgroup_bytes(int Mpad) {
+    return (size_t)Mpad * 32 * (PREC == GPMPPI_BF16 ? 2 : 4);
+}
+
+template <int PREC>
+__device__ __forceinline__ void load_kop(KOp<PREC> &k, const unsigned char *kg, int jt, int lane, int Mpad) {
+    if constexpr (PREC == GPMPPI_FP32) {
+        const float4 *K = reinterpret_cast<const float4 *>(kg) + (size_t)jt * 256 + lane;
+        k.v[0] = K[0];
+        k.v[1] = K[64];
+        k.v[2] = K[128];
+        k.v[3] = K[192];
+    } else {
+        const uint4 *K = reinterpret_cast<const uint4 *>(kg) + (size_t)jt * 128 + lane;
+        k.h[0] = K[0];
+        k.h[1] = K[64];
+        if constexpr (PREC == GPMPPI_BF16X3) {
+            const uint4 *L = reinterpret_cast<const uint4 *>(kg + (size_t)Mpad * 64) + (size_t)jt * 128 + lane;
+            k.l[0] = L[0];
+            k.l[1] = L[64];
+        }
+    }
+}
+
 __device__ __forceinline__ v8bf as_bf(uint4 u) {
     v8bf r;
     __builtin_memcpy(&r, &u, 16);
@@ -72,61 +125,129 @@ __device__ __forceinline__ v8bf as_bf(uint4 u) {
 }
 
 template <int PREC>
-__device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, const unsigned char *lds,
-                                          int jt, int lane, int Mpad) {
+__device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, const KOp<PREC> &k) {
     if constexpr (PREC == GPMPPI_FP32) {
-        const float4 *K = reinterpret_cast<const float4 *>(lds) + (size_t)jt * 256 + lane;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 kq = K[q * 64];
-            const float4 wq = b.v[q];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wq.x, kq.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wq.y, kq.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wq.z, kq.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wq.w, kq.w, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].x, k.v[q].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].y, k.v[q].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].z, k.v[q].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].w, k.v[q].w, acc, 0, 0, 0);
         }
     } else {
-        const uint4 *Kh = reinterpret_cast<const uint4 *>(lds) + (size_t)jt * 128 + lane;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const uint4 kh = Kh[h * 64];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(kh), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(k.h[h]), acc, 0, 0, 0);
             if constexpr (PREC == GPMPPI_BF16X3) {
-                const uint4 *Kl = reinterpret_cast<const uint4 *>(lds + (size_t)Mpad * 64) +
-                                  (size_t)jt * 128 + lane;
-                const uint4 kl = Kl[h * 64];
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(kl), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[h]), as_bf(kh), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(k.l[h]), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[h]), as_bf(k.h[h]), acc, 0, 0, 0);
             }
         }
     }
 }
 
-size_t rollout_lds_bytes(int precision, int Mpad) {
-    const size_t per = (precision == GPMPPI_FP32) ? 4 : (precision == GPMPPI_BF16 ? 2 : 4);
-    return (size_t)Mpad * kSamplesPerBlock * per;
+// Pair list of a wave: round i holds pairs 4i .. 4i+3, assigned in snake
+// order so that the summed pair lengths (2u + 2) balance across waves.
+__device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? 4 * i + 3 - w : 4 * i + w; }
+
+// Position in a wave's iteration sequence: pair list index i, pair u and
+// iteration it.  Forward: pairs in list order, it ascending; reverse: the
+// exact reverse of that sequence.  Every pair has an even length.
+struct Cursor {
+    int i, u, it;
+};
+
+__device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, bool rev) {
+    c.i = rev ? npairs - 1 : 0;
+    c.u = wave_pair(w, c.i);
+    c.it = rev ? 2 * c.u + 1 : 0;
 }
 
-// Tile list of a wave: round i holds tiles 4i .. 4i+3, assigned in snake
-// order so that the sum of tile heights (t + 1) is balanced across waves.
-__device__ __forceinline__ int wave_tile(int w, int i) { return (i & 1) ? 4 * i + 3 - w : 4 * i + w; }
+// Advances; returns true when the iteration just left closed its pair.
+__device__ __forceinline__ bool cursor_next(Cursor &c, int w, bool rev) {
+    if (!rev) {
+        if (++c.it > 2 * c.u + 1) {
+            ++c.i;
+            c.u = wave_pair(w, c.i);
+            c.it = 0;
+            return true;
+        }
+    } else {
+        if (--c.it < 0) {
+            --c.i;
+            c.u = wave_pair(w, c.i);
+            c.it = 2 * c.u + 1;
+            return true;
+        }
+    }
+    return false;
+}
 
-constexpr int ring_depth(int prec) { return prec == GPMPPI_FP32 ? 4 : 8; }
+__device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (c.u + 1) + c.it); }
 
-// One GP output for the 32 samples of the block.  Must be called by all 256
-// threads.  qs: this thread's sample query scaled by s_o.  Returns the GP
-// mean and the predictive variance of that sample (identical on its 8 lanes).
-template <int PREC>
-__device__ __forceinline__ void gp_output(const GpDev &g, int o, const float qs[4], int s, int r,
-                                          unsigned char *lds, float *red, float &mean_out,
-                                          float &var_out) {
+
+template <int PREC, int G>
+struct Shapes {
+    static constexpr int B = 32 * G;                 // samples per block
+    static constexpr int parts = kWaves * (2 / G);   // loop splitters: waves (x half-waves for G = 1)
+};
+
+// Dynamic LDS layout: [G k-operand groups][zs: Mpad float4][alpha: Mpad float]
+template <int PREC, int G>
+__host__ __device__ constexpr size_t dyn_lds_bytes(int Mpad) {
+    return G * kgroup_bytes<PREC>(Mpad) + (size_t)Mpad * 20;
+}
+
+// One GP output for the B samples of the block; called by all threads.
+// Returns the sample's GP mean and predictive variance.
+// Inputs (zs, alpha) of output o held in registers between their global load
+// and their store to LDS: thread t owns float4 slots t, t + 256, ... of the
+// Mpad zs entries followed by the Mpad / 4 alpha quads (at most 1280 slots).
+struct StagedInputs {
+    float4 v[5];
+};
+
+__device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
+    const int Mpad = g.Mpad, nz = Mpad, na = Mpad >> 2;
+    const float4 *zsrc = reinterpret_cast<const float4 *>(g.zs) + (size_t)o * Mpad;
+    const float4 *asrc = reinterpret_cast<const float4 *>(g.alpha + (size_t)o * Mpad);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const int slot = threadIdx.x + r * kThreads;
+        if (slot < nz) st.v[r] = zsrc[slot];
+        else if (slot < nz + na) st.v[r] = asrc[slot - nz];
+    }
+}
+
+__device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev &g, unsigned char *lds,
+                                            size_t zs_off) {
+    const int Mpad = g.Mpad;
+    float4 *dst = reinterpret_cast<float4 *>(lds + zs_off);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        const int slot = threadIdx.x + r * kThreads;
+        if (slot < Mpad + (Mpad >> 2)) dst[slot] = st.v[r];
+    }
+}
+
+// One GP output for the B samples of the block; called by all threads with
+// the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
+// next_o replace them before returning (the caller synchronises before the
+// next use).  Returns the sample's GP mean and predictive variance.
+template <int PREC, int G>
+__device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
+                                          bool rev, unsigned char *lds, float *pred, float *vred,
+                                          float &mean_out, float &var_out) {
+    using S = Shapes<PREC, G>;
     const int Mpad = g.Mpad;
     const int nchunk = Mpad >> 3;
-    const float4 *zs = reinterpret_cast<const float4 *>(g.zs) + (size_t)o * Mpad;
-    const float *al = g.alpha + (size_t)o * Mpad;
+    const float4 *zs = reinterpret_cast<const float4 *>(lds + G * kgroup_bytes<PREC>(Mpad));
+    const float *al = reinterpret_cast<const float *>(zs + Mpad);
     const float c2 = g.c2[o];
+    const int grp = sl >> 5, s32 = sl & 31;
+    unsigned char *kg = lds + grp * kgroup_bytes<PREC>(Mpad);
     float msum = 0.0f;
-    for (int c = r; c < nchunk; c += kLanesPerSample) {
+    for (int c = part; c < nchunk; c += S::parts) {
         float kv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -150,9 +271,9 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, const float qs[
         msum = fmaf(kv[6], a1.z, msum);
         msum = fmaf(kv[7], a1.w, msum);
         if constexpr (PREC == GPMPPI_FP32) {
-            float4 *K = reinterpret_cast<float4 *>(lds) + (size_t)c * 64;
-            K[s] = make_float4(kv[0], kv[2], kv[4], kv[6]);
-            K[32 + s] = make_float4(kv[1], kv[3], kv[5], kv[7]);
+            float4 *K = reinterpret_cast<float4 *>(kg) + (size_t)c * 64;
+            K[s32] = make_float4(kv[0], kv[2], kv[4], kv[6]);
+            K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
         } else {
             uint16_t hb[8];
 #pragma unroll
@@ -162,8 +283,8 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, const float qs[
             hv.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
             hv.z = (uint32_t)hb[4] | ((uint32_t)hb[5] << 16);
             hv.w = (uint32_t)hb[6] | ((uint32_t)hb[7] << 16);
-            const int idx = (c >> 1) * 64 + s + 32 * (c & 1);
-            reinterpret_cast<uint4 *>(lds)[idx] = hv;
+            const int idx = (c >> 1) * 64 + s32 + 32 * (c & 1);
+            reinterpret_cast<uint4 *>(kg)[idx] = hv;
             if constexpr (PREC == GPMPPI_BF16X3) {
                 uint16_t lb[8];
 #pragma unroll
@@ -173,93 +294,125 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, const float qs[
                 lv.y = (uint32_t)lb[2] | ((uint32_t)lb[3] << 16);
                 lv.z = (uint32_t)lb[4] | ((uint32_t)lb[5] << 16);
                 lv.w = (uint32_t)lb[6] | ((uint32_t)lb[7] << 16);
-                reinterpret_cast<uint4 *>(lds + (size_t)Mpad * 64)[idx] = lv;
+                reinterpret_cast<uint4 *>(kg + (size_t)Mpad * 64)[idx] = lv;
             }
         }
     }
-    msum += shfl_xor(msum, 1);
-    msum += shfl_xor(msum, 2);
-    msum += shfl_xor(msum, 4);
+    // per-part partial means: the lanes of a part hold distinct samples
+    pred[part * S::B + sl] = msum;
     __syncthreads();
+    StagedInputs st;
+    if (next_o >= 0) stage_load(st, g, next_o);
 
     // ---- variance contraction on the matrix cores
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int NT = g.NT;
-    const int rounds = (NT + 3) >> 2;
-    int ntiles = rounds;
-    if (wave_tile(w, rounds - 1) >= NT) ntiles = rounds - 1;
-    int nsteps = 0;
-    for (int i = 0; i < ntiles; ++i) nsteps += wave_tile(w, i) + 1;
+    const int NP = g.NT >> 1;
+    const int rounds = (NP + 3) >> 2;
+    int npairs = rounds;
+    if (wave_pair(w, rounds - 1) >= NP) npairs = rounds - 1;
+    int nit = 0;
+    for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair(w, i) + 2;   // even
 
-    constexpr int D = ring_depth(PREC);
-    WBlock<PREC> ring[D];
-    int pi = 0, pjt = 0;   // prefetch position (tile list index, column block)
+    const unsigned char *kgrp[G];
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-        if (u < nsteps) {
-            const int t = wave_tile(w, pi);
-            load_wblock<PREC>(ring[u], g, o, t * (t + 1) / 2 + pjt, lane);
-            if (++pjt > t) {
-                ++pi;
-                pjt = 0;
-            }
-        }
+    for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
+    // register ring of two iterations (two W blocks each); k operand one iteration ahead
+    WBlock<PREC> ring[2][2];
+    KOp<PREC> kcur[G];
+    v16f acc[2][G];
+    float sq[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        acc[0][gg] = v16f{};
+        acc[1][gg] = v16f{};
+        sq[gg] = 0.0f;
     }
-    v16f acc = {};
-    float sq = 0.0f;
-    int ci = 0, cjt = 0;
-    int ct = wave_tile(w, 0);
-    for (int base = 0; base < nsteps; base += D) {
+    Cursor pc, mc;   // prefetch and compute cursors
+    if (nit > 0) {
+        cursor_start(pc, w, npairs, rev);
+        cursor_start(mc, w, npairs, rev);
 #pragma unroll
-        for (int u = 0; u < D; ++u) {
-            if (base + u < nsteps) {
-                const WBlock<PREC> cur = ring[u];
-                if (base + u + D < nsteps) {
-                    const int t = wave_tile(w, pi);
-                    load_wblock<PREC>(ring[u], g, o, t * (t + 1) / 2 + pjt, lane);
-                    if (++pjt > t) {
-                        ++pi;
-                        pjt = 0;
+        for (int r = 0; r < 2; ++r) {
+            const int b0 = pair_block(pc);
+            load_wblock<PREC>(ring[r][0], g, o, b0, lane);
+            load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
+            cursor_next(pc, w, rev);
+        }
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
+    }
+    for (int base = 0; base < nit; base += 2) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const WBlock<PREC> wa = ring[r][0], wb = ring[r][1];
+            if (base + r + 2 < nit) {
+                const int b0 = pair_block(pc);
+                load_wblock<PREC>(ring[r][0], g, o, b0, lane);
+                load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
+                cursor_next(pc, w, rev);
+            }
+            KOp<PREC> kuse[G];
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) kuse[gg] = kcur[gg];
+            const bool pair_end = cursor_next(mc, w, rev);
+            if (base + r + 1 < nit) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
+            }
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                mma_block<PREC>(acc[0][gg], wa, kuse[gg]);
+                mma_block<PREC>(acc[1][gg], wb, kuse[gg]);
+            }
+            if (pair_end) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        sq[gg] = fmaf(acc[0][gg][e], acc[0][gg][e], sq[gg]);
+                        sq[gg] = fmaf(acc[1][gg][e], acc[1][gg][e], sq[gg]);
                     }
-                }
-                mma_block<PREC>(acc, cur, lds, cjt, lane, Mpad);
-                if (++cjt > ct) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) sq = fmaf(acc[e], acc[e], sq);
-                    acc = v16f{};
-                    ++ci;
-                    cjt = 0;
-                    ct = wave_tile(w, ci);
+                    acc[0][gg] = v16f{};
+                    acc[1][gg] = v16f{};
                 }
             }
         }
     }
-    sq += shfl_xor(sq, 32);
-    if (lane < 32) red[w * 32 + lane] = sq;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        sq[gg] += shfl_xor(sq[gg], 32);
+        if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
+    }
     __syncthreads();
-    const float v2 = (red[s] + red[32 + s]) + (red[64 + s] + red[96 + s]);
+    if (next_o >= 0) stage_store(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
+    float v2 = 0.0f, m = 0.0f;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) v2 += vred[ww * S::B + sl];
+#pragma unroll
+    for (int p = 0; p < S::parts; ++p) m += pred[p * S::B + sl];
     var_out = g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2);
-    mean_out = msum;
+    mean_out = m;
 }
 
-__device__ __forceinline__ float min8(float v) {
-    v = fminf(v, shfl_xor(v, 1));
-    v = fminf(v, shfl_xor(v, 2));
-    v = fminf(v, shfl_xor(v, 4));
-    return v;
-}
-
-template <int PREC>
+template <int PREC, int G>
 __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
+    using S = Shapes<PREC, G>;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float red[kWaves * 32];
+    __shared__ float pred[S::parts * S::B];
+    __shared__ float ored[S::parts * S::B];
+    __shared__ float vred[kWaves * S::B];
     const int tid = threadIdx.x;
-    const int s = tid / kLanesPerSample, r = tid % kLanesPerSample;
-    const int sg = blockIdx.x * kSamplesPerBlock + s;
+    const int lane = tid & 63, w = tid >> 6;
+    const int sl = lane % S::B;                     // sample within the block
+    const int part = (G == 2) ? w : 2 * w + (lane >> 5);
+    const int wu = __builtin_amdgcn_readfirstlane(w);   // wave-uniform loop splitter for G = 2
+    const int sg = blockIdx.x * S::B + sl;
     const bool valid = sg < a.K;
-    const bool writer = valid && r == 0;
+    const bool writer = valid && w == 0 && lane < S::B;
     const int K = a.K;
+    const int Mpad = a.gp.Mpad;
+    const size_t zs_off = G * kgroup_bytes<PREC>(Mpad);
 
     NoiseParams np = a.noise;
     {
@@ -272,18 +425,17 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
     const CostWeights cw = a.cw;
     const Geometry &geo = a.geo;
 
-    float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w = a.x0[4];
-    // Sigma (symmetric), Sigma(0) = 0
+    float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w_ = a.x0[4];
     float p00 = 0, p01 = 0, p02 = 0, p03 = 0, p04 = 0, p11 = 0, p12 = 0, p13 = 0, p14 = 0, p22 = 0,
           p23 = 0, p24 = 0, p33 = 0, p34 = 0, p44 = 0;
-    float S = 0.0f, Sc = 0.0f, disc = 1.0f;
+    float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
 
     if (writer && a.trace.x_d) {
         a.trace.x_d[0 * K + sg] = X;
         a.trace.x_d[1 * K + sg] = Y;
         a.trace.x_d[2 * K + sg] = th;
         a.trace.x_d[3 * K + sg] = v;
-        a.trace.x_d[4 * K + sg] = w;
+        a.trace.x_d[4 * K + sg] = w_;
     }
     if (writer && a.trace.sxy_d) {
         a.trace.sxy_d[0 * K + sg] = 0.0f;
@@ -291,15 +443,24 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
         a.trace.sxy_d[2 * K + sg] = 0.0f;
     }
 
+    {   // inputs of output 0 (the first output of step 0)
+        StagedInputs st;
+        stage_load(st, a.gp, 0);
+        stage_store(st, a.gp, lds, zs_off);
+    }
     for (int k = 0; k < a.T; ++k) {
+        // even steps: outputs 0 then 1; odd steps: 1 then 0 (and blocks reversed)
+        const bool rev = (k & 1) != 0;
         const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
-        const float q[4] = {v, w, u.x, u.y};
+        const float q[4] = {v, w_, u.x, u.y};
         float m[2], s2[2];
 #pragma unroll
-        for (int o = 0; o < 2; ++o) {
+        for (int oo = 0; oo < 2; ++oo) {
+            const int o = rev ? 1 - oo : oo;
+            __syncthreads();   // staged inputs visible; previous k-operand readers are done
             const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
                                  q[3] * a.gp.scale[o][3]};
-            gp_output<PREC>(a.gp, o, qs, s, r, lds, red, m[o], s2[o]);
+            gp_output<PREC, G>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, lds, pred, vred, m[o], s2[o]);
         }
 
         // ---- mean: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2, 10)
@@ -310,9 +471,9 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
         const float a33 = dy.a33, a44 = dy.a44;
         const float Xn = X + dt * v * cth;
         const float Yn = Y + dt * v * sth;
-        const float thn = th + dt * w;
+        const float thn = th + dt * w_;
         const float vn = v + (dy.dt_tau_v * (u.x - v) + dt * m[0]);
-        const float wn = w + (dy.dt_tau_w * (u.y - w) + dt * m[1]);
+        const float wn = w_ + (dy.dt_tau_w * (u.y - w_) + dt * m[1]);
 
         // ---- covariance: Sigma+ = A Sigma A^T + dt^2 diag(0, 0, 0, s2_v, s2_w) (Eq. 10)
         // B = A Sigma (rows), then Sigma+_ij = sum_n B_in A_jn for i <= j.
@@ -321,46 +482,33 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
                     b04 = p04 + a02 * p24 + a03 * p34;
         const float b11 = p11 + a12 * p12 + a13 * p13, b12 = p12 + a12 * p22 + a13 * p23,
                     b13 = p13 + a12 * p23 + a13 * p33, b14 = p14 + a12 * p24 + a13 * p34;
-        const float b10 = p01 + a12 * p02 + a13 * p03;
         const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
-        const float b20 = p02 + a24 * p04, b21 = p12 + a24 * p14;
         const float b33 = a33 * p33, b34 = a33 * p34;
         const float b44 = a44 * p44;
-        (void)b20;
-        (void)b21;
-        (void)b10;
-        const float n00 = b00 + a02 * b02 + a03 * b03;
-        const float n01 = b01 + a12 * b02 + a13 * b03;
-        const float n02 = b02 + a24 * b04;
-        const float n03 = a33 * b03;
-        const float n04 = a44 * b04;
-        const float n11 = b11 + a12 * b12 + a13 * b13;
-        const float n12 = b12 + a24 * b14;
-        const float n13 = a33 * b13;
-        const float n14 = a44 * b14;
-        const float n22 = b22 + a24 * b24;
-        const float n23 = a33 * b23;
-        const float n24 = a44 * b24;
-        const float n33 = a33 * b33 + dt * dt * s2[0];
-        const float n34 = a44 * b34;
-        const float n44 = a44 * b44 + dt * dt * s2[1];
-        p00 = n00; p01 = n01; p02 = n02; p03 = n03; p04 = n04;
-        p11 = n11; p12 = n12; p13 = n13; p14 = n14;
-        p22 = n22; p23 = n23; p24 = n24;
-        p33 = n33; p34 = n34; p44 = n44;
-        X = Xn; Y = Yn; th = thn; v = vn; w = wn;
+        p00 = b00 + a02 * b02 + a03 * b03;
+        p01 = b01 + a12 * b02 + a13 * b03;
+        p02 = b02 + a24 * b04;
+        p03 = a33 * b03;
+        p04 = a44 * b04;
+        p11 = b11 + a12 * b12 + a13 * b13;
+        p12 = b12 + a24 * b14;
+        p13 = a33 * b13;
+        p14 = a44 * b14;
+        p22 = b22 + a24 * b24;
+        p23 = a33 * b23;
+        p24 = a44 * b24;
+        p33 = a33 * b33 + dt * dt * s2[0];
+        p34 = a44 * b34;
+        p44 = a44 * b44 + dt * dt * s2[1];
+        X = Xn; Y = Yn; th = thn; v = vn; w_ = wn;
 
         // ---- chance constraints at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16)
         const float sa = p00, sb = p01, sc = p11;
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
-        float dl;
-        if (geo.path_kind == 0) {
-            const float dx = X - geo.cx, dyy = Y - geo.cy;
-            dl = fabsf(sqrtf(dx * dx + dyy * dyy) - geo.R);
-        } else {
-            float best = INFINITY;
-            for (int i = r; i < geo.P; i += kLanesPerSample) {
+        float best = INFINITY;   // squared distance to the polyline (this part's segments)
+        if (geo.path_kind != 0) {
+            for (int i = (G == 2 ? wu : part); i < geo.P; i += S::parts) {
                 const float4 sgm = geo.seg[i];
                 const float rx = X - sgm.x, ry = Y - sgm.y;
                 float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
@@ -368,11 +516,9 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
                 const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
                 best = fminf(best, ex * ex + ey * ey);
             }
-            dl = sqrtf(min8(best));
         }
-        const float rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
         float om = INFINITY;
-        for (int j = r; j < geo.n_obs; j += kLanesPerSample) {
+        for (int j = (G == 2 ? wu : part); j < geo.n_obs; j += S::parts) {
             const float4 ob = geo.obs[j];
             const float dx = X - ob.x, dyy = Y - ob.y;
             const float rho2 = dx * dx + dyy * dyy;
@@ -380,7 +526,25 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
             const float vn_dir = rho > 0.0f ? (sa * dx * dx + 2.0f * sb * dx * dyy + sc * dyy * dyy) / rho2 : lmax;
             om = fminf(om, (rho - ob.z) - geo.z_p * sqrtf(fmaxf(vn_dir, 0.0f)));
         }
-        om = min8(om);
+        __syncthreads();   // readers of the last output's partial sums are done
+        pred[part * S::B + sl] = best;
+        ored[part * S::B + sl] = om;
+        __syncthreads();
+        float best_all = INFINITY, om_all = INFINITY;
+#pragma unroll
+        for (int p = 0; p < S::parts; ++p) {
+            best_all = fminf(best_all, pred[p * S::B + sl]);
+            om_all = fminf(om_all, ored[p * S::B + sl]);
+        }
+        om = om_all;
+        float dl;
+        if (geo.path_kind == 0) {
+            const float dx = X - geo.cx, dyy = Y - geo.cy;
+            dl = fabsf(sqrtf(dx * dx + dyy * dyy) - geo.R);
+        } else {
+            dl = sqrtf(best_all);
+        }
+        const float rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
 
         // ---- stage cost (Eqs. 11-12 terms), Kahan-compensated sum (Eq. 5)
         const float dv = cw.v_des - v;
@@ -389,9 +553,9 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
         if (om <= 0.0f) c += cw.w_obs;
         {
             const float yk = c - Sc;
-            const float tk = S + yk;
-            Sc = (tk - S) - yk;
-            S = tk;
+            const float tk = S_ + yk;
+            Sc = (tk - S_) - yk;
+            S_ = tk;
         }
         disc *= cw.discount;
 
@@ -404,7 +568,7 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
                 xd[1 * K + sg] = Y;
                 xd[2 * K + sg] = th;
                 xd[3 * K + sg] = v;
-                xd[4 * K + sg] = w;
+                xd[4 * K + sg] = w_;
             }
             if (tr.sxy_d) {
                 float *sd = tr.sxy_d + (kk + 1) * 3 * K;
@@ -429,32 +593,67 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
             }
         }
     }
-    if (writer) a.costs[sg] = S;
+    if (writer) a.costs[sg] = S_;
 }
 
-template <int PREC>
+template <int PREC, int G>
 __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const float *q, int n, float *mean,
                                                               float *var) {
+    using S = Shapes<PREC, G>;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float red[kWaves * 32];
+    __shared__ float pred[S::parts * S::B];
+    __shared__ float vred[kWaves * S::B];
     const int tid = threadIdx.x;
-    const int s = tid / kLanesPerSample, r = tid % kLanesPerSample;
-    const int sg = blockIdx.x * kSamplesPerBlock + s;
-    const int sl = sg < n ? sg : n - 1;
-    const float4 qq = reinterpret_cast<const float4 *>(q)[sl];
+    const int lane = tid & 63, w = tid >> 6;
+    const int sl = lane % S::B;
+    const int part = (G == 2) ? w : 2 * w + (lane >> 5);
+    const int sg = blockIdx.x * S::B + sl;
+    const int sc = sg < n ? sg : n - 1;
+    const float4 qq = reinterpret_cast<const float4 *>(q)[sc];
     const float qv[4] = {qq.x, qq.y, qq.z, qq.w};
+    const size_t zs_off = G * kgroup_bytes<PREC>(g.Mpad);
+    {
+        StagedInputs st;
+        stage_load(st, g, 0);
+        stage_store(st, g, lds, zs_off);
+    }
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
+        __syncthreads();
         const float qs[4] = {qv[0] * g.scale[o][0], qv[1] * g.scale[o][1], qv[2] * g.scale[o][2],
                              qv[3] * g.scale[o][3]};
         float m, s2;
-        gp_output<PREC>(g, o, qs, s, r, lds, red, m, s2);
-        if (sg < n && r == 0) {
+        gp_output<PREC, G>(g, o, o == 0 ? 1 : -1, qs, part, sl, false, lds, pred, vred, m, s2);
+        if (sg < n && w == 0 && lane < S::B) {
             mean[(size_t)o * n + sg] = m;
             var[(size_t)o * n + sg] = s2;
         }
     }
 }
+
+// Sample groups per block: two when both groups' k operand and the staged
+// inputs fit the 160 KB LDS of a CDNA4 compute unit, else one.
+static int groups_for(int precision, int Mpad) {
+    const size_t budget = 160 * 1024 - 8 * 1024;
+    size_t need2 = 0;
+    switch (precision) {
+        case GPMPPI_FP32: need2 = dyn_lds_bytes<GPMPPI_FP32, 2>(Mpad); break;
+        case GPMPPI_BF16: need2 = dyn_lds_bytes<GPMPPI_BF16, 2>(Mpad); break;
+        default: need2 = dyn_lds_bytes<GPMPPI_BF16X3, 2>(Mpad); break;
+    }
+    return need2 <= budget ? 2 : 1;
+}
+
+size_t rollout_lds_bytes(int precision, int Mpad) {
+    const int G = groups_for(precision, Mpad);
+    switch (precision) {
+        case GPMPPI_FP32: return G == 2 ? dyn_lds_bytes<GPMPPI_FP32, 2>(Mpad) : dyn_lds_bytes<GPMPPI_FP32, 1>(Mpad);
+        case GPMPPI_BF16: return G == 2 ? dyn_lds_bytes<GPMPPI_BF16, 2>(Mpad) : dyn_lds_bytes<GPMPPI_BF16, 1>(Mpad);
+        default: return G == 2 ? dyn_lds_bytes<GPMPPI_BF16X3, 2>(Mpad) : dyn_lds_bytes<GPMPPI_BF16X3, 1>(Mpad);
+    }
+}
+
+int rollout_samples_per_block(int precision, int Mpad) { return 32 * groups_for(precision, Mpad); }
 
 template <typename F>
 static hipError_t set_lds(F *fn, size_t bytes) {
@@ -462,47 +661,47 @@ static hipError_t set_lds(F *fn, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int PREC, int G>
+static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
+    const size_t lds = dyn_lds_bytes<PREC, G>(a.gp.Mpad);
+    hipError_t e = set_lds(rollout_kernel<PREC, G>, lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((a.K + 32 * G - 1) / (32 * G));
+    hipLaunchKernelGGL((rollout_kernel<PREC, G>), grid, dim3(kThreads), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_rollout(const RolloutArgs &a, int precision, hipStream_t st) {
-    const size_t lds = rollout_lds_bytes(precision, a.gp.Mpad);
-    const dim3 grid((a.K + kSamplesPerBlock - 1) / kSamplesPerBlock);
-    hipError_t e;
+    const int G = groups_for(precision, a.gp.Mpad);
     switch (precision) {
-        case GPMPPI_FP32:
-            if ((e = set_lds(rollout_kernel<GPMPPI_FP32>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(rollout_kernel<GPMPPI_FP32>, grid, dim3(kThreads), lds, st, a);
-            break;
-        case GPMPPI_BF16:
-            if ((e = set_lds(rollout_kernel<GPMPPI_BF16>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(rollout_kernel<GPMPPI_BF16>, grid, dim3(kThreads), lds, st, a);
-            break;
-        default:
-            if ((e = set_lds(rollout_kernel<GPMPPI_BF16X3>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(rollout_kernel<GPMPPI_BF16X3>, grid, dim3(kThreads), lds, st, a);
-            break;
+        case GPMPPI_FP32: return G == 2 ? launch_rollout_t<GPMPPI_FP32, 2>(a, st) : launch_rollout_t<GPMPPI_FP32, 1>(a, st);
+        case GPMPPI_BF16: return G == 2 ? launch_rollout_t<GPMPPI_BF16, 2>(a, st) : launch_rollout_t<GPMPPI_BF16, 1>(a, st);
+        default: return G == 2 ? launch_rollout_t<GPMPPI_BF16X3, 2>(a, st) : launch_rollout_t<GPMPPI_BF16X3, 1>(a, st);
     }
+}
+
+template <int PREC, int G>
+static hipError_t launch_predict_t(const GpDev &g, const float *q, int n, float *mean, float *var,
+                                   hipStream_t st) {
+    const size_t lds = dyn_lds_bytes<PREC, G>(g.Mpad);
+    hipError_t e = set_lds(gp_predict_kernel<PREC, G>, lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((n + 32 * G - 1) / (32 * G));
+    hipLaunchKernelGGL((gp_predict_kernel<PREC, G>), grid, dim3(kThreads), lds, st, g, q, n, mean, var);
     return hipGetLastError();
 }
 
 hipError_t launch_gp_predict(const GpDev &g, int precision, const float *q, int n, float *mean, float *var,
                              hipStream_t st) {
-    const size_t lds = rollout_lds_bytes(precision, g.Mpad);
-    const dim3 grid((n + kSamplesPerBlock - 1) / kSamplesPerBlock);
-    hipError_t e;
+    const int G = groups_for(precision, g.Mpad);
     switch (precision) {
-        case GPMPPI_FP32:
-            if ((e = set_lds(gp_predict_kernel<GPMPPI_FP32>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(gp_predict_kernel<GPMPPI_FP32>, grid, dim3(kThreads), lds, st, g, q, n, mean, var);
-            break;
-        case GPMPPI_BF16:
-            if ((e = set_lds(gp_predict_kernel<GPMPPI_BF16>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(gp_predict_kernel<GPMPPI_BF16>, grid, dim3(kThreads), lds, st, g, q, n, mean, var);
-            break;
-        default:
-            if ((e = set_lds(gp_predict_kernel<GPMPPI_BF16X3>, lds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(gp_predict_kernel<GPMPPI_BF16X3>, grid, dim3(kThreads), lds, st, g, q, n, mean, var);
-            break;
+        case GPMPPI_FP32: return G == 2 ? launch_predict_t<GPMPPI_FP32, 2>(g, q, n, mean, var, st)
+                                        : launch_predict_t<GPMPPI_FP32, 1>(g, q, n, mean, var, st);
+        case GPMPPI_BF16: return G == 2 ? launch_predict_t<GPMPPI_BF16, 2>(g, q, n, mean, var, st)
+                                        : launch_predict_t<GPMPPI_BF16, 1>(g, q, n, mean, var, st);
+        default: return G == 2 ? launch_predict_t<GPMPPI_BF16X3, 2>(g, q, n, mean, var, st)
+                               : launch_predict_t<GPMPPI_BF16X3, 1>(g, q, n, mean, var, st);
     }
-    return hipGetLastError();
 }
 
 }  // namespace gpmppi

@@ -275,11 +275,12 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->device = dev;
     c->params = *params;
     c->M = gp[0].M;
-    c->Mpad = (c->M + 31) / 32 * 32;
+    c->Mpad = (c->M + 63) / 64 * 64;   // an even number of 32-row tiles (pairs of row tiles)
     c->NT = c->Mpad / 32;
     const int Mpad = c->Mpad, NT = c->NT;
-    c->w32_stride = (long long)NT * (NT + 1) / 2 * 256;
-    c->wb_stride = (long long)NT * (NT + 1) / 2 * 128;
+    const int NP = (NT + 1) / 2;   // row-tile pairs; pair u holds 2 (2u + 2) blocks
+    c->w32_stride = (long long)2 * NP * (NP + 1) * 256;
+    c->wb_stride = (long long)2 * NP * (NP + 1) * 128;
     c->n_obs = obstacles->n;
     const int P = path->kind == 1 ? path->P : 0;
 
