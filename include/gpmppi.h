@@ -172,6 +172,43 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *ctx, float *x_d, float *U_d, uint64
                                  double amplitude, float *x_hist_d, float *U0_hist_d,
                                  int32_t use_graph, void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (uneven K, T, M, obstacle count and track) run
+ * together: one persistent rollout launch whose workgroups take (problem,
+ * sample block) items, longest first, from a device counter, then one update
+ * launch with a workgroup per (problem, horizon step).  Results of a problem
+ * do not depend on the schedule.  All problems share one precision form. */
+typedef struct gpmppi_batch gpmppi_batch;
+
+/* Creates n problems on the current device, each exactly as gpmppi_init would
+ * (arrays: params[n], gp[2n] (problem p: gp[2p], gp[2p+1]), obstacles[n],
+ * paths[n]).  Synchronises. */
+gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const gpmppi_gp gp[],
+                                const gpmppi_obstacles obstacles[], const gpmppi_path paths[],
+                                gpmppi_batch **out);
+
+/* Packed layouts of the batched device arrays: problem p owns the floats
+ * U[U_off[p] .. U_off[p+1]) ([T_p][2]) and costs/weights [K_off[p] .. K_off[p+1]).
+ * Writes n + 1 entries to each non-NULL array. */
+gpmppi_status gpmppi_batch_layout(const gpmppi_batch *b, int64_t *U_off, int64_t *K_off);
+
+/* One MPPI iteration of every problem (as gpmppi_step per problem, with
+ * Philox counter word 2 = that problem's problem_id).  x0_d [n][5], U_d and
+ * U_out_d packed controls (U_out_d may alias U_d), costs_d and weights_d
+ * (may be NULL) packed per-sample arrays. */
+gpmppi_status gpmppi_batch_step(gpmppi_batch *b, const float *x0_d, const float *U_d, uint64_t seed,
+                                float *U_out_d, float *costs_d, float *weights_d, void *stream);
+
+/* n_steps closed-loop steps of every problem, all on device: iteration keyed
+ * by seed0 + t, plant step with U'_0, warm-start shift.  x_d [n][5] and U_d
+ * (packed) are updated in place; x_hist_d [n_steps + 1][n][5] may be NULL.
+ * use_graph != 0 captures one step in a HIP graph and replays it. */
+gpmppi_status gpmppi_batch_closed_loop(gpmppi_batch *b, float *x_d, float *U_d, uint64_t seed0, int32_t n_steps,
+                                       double amplitude, float *x_hist_d, int32_t use_graph, void *stream);
+
+/* Frees the batch (NULL is accepted). */
+void gpmppi_batch_destroy(gpmppi_batch *b);
+
 /* Philox4x32-10 (Salmon et al., SC'11) raw output for n counters:
  * ctr_d [n][4] device (words), out_d [n][4] device; key = (seed lo, seed hi). */
 gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uint32_t *out_d,

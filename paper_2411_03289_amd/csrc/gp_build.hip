@@ -228,27 +228,36 @@ __global__ void pack_w_kernel(const double *W, int M, int Mpad, float4 *w32, uin
 }
 
 __global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int Mpad, double s0, double s1,
-                                double s2, double s3, float *zs, float *al) {
+                                double s2, double s3, double c2, float *zs, float *al, float *zs2, float *cza) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Mpad) return;
+    double z[4] = {0.0, 0.0, 0.0, 0.0}, a = 0.0;
     if (j < M) {
-        zs[4 * j] = (float)(Z[4 * j] * s0);
-        zs[4 * j + 1] = (float)(Z[4 * j + 1] * s1);
-        zs[4 * j + 2] = (float)(Z[4 * j + 2] * s2);
-        zs[4 * j + 3] = (float)(Z[4 * j + 3] * s3);
-        al[j] = (float)alpha[j];
-    } else {
-        zs[4 * j] = zs[4 * j + 1] = zs[4 * j + 2] = zs[4 * j + 3] = 0.0f;
-        al[j] = 0.0f;
+        z[0] = Z[4 * j] * s0;
+        z[1] = Z[4 * j + 1] * s1;
+        z[2] = Z[4 * j + 2] * s2;
+        z[3] = Z[4 * j + 3] * s3;
+        a = alpha[j];
     }
+    const float zf[4] = {(float)z[0], (float)z[1], (float)z[2], (float)z[3]};
+    double zz = 0.0;
+    for (int d = 0; d < 4; ++d) {
+        zs[4 * j + d] = zf[d];
+        zs2[4 * j + d] = 2.0f * zf[d];
+        zz += (double)zf[d] * (double)zf[d];
+    }
+    al[j] = (float)a;
+    cza[2 * j] = (float)(c2 - zz);
+    cza[2 * j + 1] = (float)a;
 }
 
-hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], float *zs,
-                          float *alpha, float4 *w32, uint4 *wbh, uint4 *wbl, hipStream_t st) {
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
+                          float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
+                          hipStream_t st) {
     const int NP = (Mpad / 32 + 1) / 2;
     hipLaunchKernelGGL(pack_w_kernel, dim3(2 * NP * (NP + 1)), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
     hipLaunchKernelGGL(pack_vec_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.Z, b.alpha, M, Mpad,
-                       scale[0], scale[1], scale[2], scale[3], zs, alpha);
+                       scale[0], scale[1], scale[2], scale[3], c2, zs, alpha, zs2, cza);
     return hipGetLastError();
 }
 

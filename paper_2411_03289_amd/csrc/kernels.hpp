@@ -15,9 +15,14 @@ namespace gpmppi {
 //  alpha  [2][Mpad]     (K + sn^2 I)^-1 y, zero beyond M
 //  w32    packed FP32 blocks of W = L^-1 (see pack layout in gp_build.hip)
 //  wbh/wbl packed BF16 hi / lo splits of the same blocks
+//  zs2    [2][Mpad][4]  2 zs, and cza [2][Mpad][2] (c2_o - |zs_oj|^2, alpha_oj):
+//                       the expanded exponent c2 - |q|^2 - |zs|^2 + 2 q.zs used by
+//                       the BF16 forms
 struct GpDev {
     const float *zs;
     const float *alpha;
+    const float *zs2;
+    const float *cza;
     const float4 *w32;
     const uint4 *wbh;
     const uint4 *wbl;
@@ -61,6 +66,7 @@ struct RolloutArgs {
     uint64_t seed;
     const uint32_t *step_counter;   // if non-NULL, seed + *step_counter keys the noise
     int K, T;
+    int rotate;                     // start each block's walk over W at a block-dependent pair
     const float *x0;                // [5]
     const float *U;                 // [T][2]
     float *costs;                   // [K]
@@ -81,7 +87,30 @@ struct UpdateArgs {
 };
 
 size_t rollout_lds_bytes(int precision, int Mpad);
+int rollout_groups(int precision, int Mpad);
 hipError_t launch_rollout(const RolloutArgs &a, int precision, hipStream_t st);
+hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
+                                int precision, int G, int Mpad_max, int grid, hipStream_t st);
+hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st);
+hipError_t launch_plant_shift_batch(float *x, float *U, const long long *U_off, const int *T, const Dyn *dyn,
+                                    float amplitude, const uint32_t *step_counter, float *x_hist, int n,
+                                    hipStream_t st);
+hipError_t launch_counter_add(uint32_t *counter, uint32_t v, hipStream_t st);
+
+// Pointers of one batched call, patched into the per-problem argument tables
+// on the device (problem p: x0 + 5p, U + U_off[p], costs + K_off[p], ...).
+struct BatchPtrs {
+    const float *x0;
+    const float *U;
+    float *U_out;
+    float *costs;
+    float *weights;        // may be NULL
+    uint64_t seed;
+    const uint32_t *step_counter;   // may be NULL
+    const long long *U_off;
+    const long long *K_off;
+};
+hipError_t launch_batch_patch(RolloutArgs *ra, UpdateArgs *ua, int n, BatchPtrs ptrs, hipStream_t st);
 hipError_t launch_gp_predict(const GpDev &g, int precision, const float *q, int n, float *mean,
                              float *var, hipStream_t st);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
@@ -102,7 +131,8 @@ struct GpBuildBuffers {
 };
 hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double ell[4], double sf2,
                            double sn2, hipStream_t st);
-hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], float *zs,
-                          float *alpha, float4 *w32, uint4 *wbh, uint4 *wbl, hipStream_t st);
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
+                          float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
+                          hipStream_t st);
 
 }  // namespace gpmppi

@@ -150,41 +150,46 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
 // order so that the summed pair lengths (2u + 2) balance across waves.
 __device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? 4 * i + 3 - w : 4 * i + w; }
 
-// Position in a wave's iteration sequence: pair list index i, pair u and
-// iteration it.  Forward: pairs in list order, it ascending; reverse: the
-// exact reverse of that sequence.  Every pair has an even length.
+// Position in a wave's iteration sequence: n pairs visited so far, list
+// index i = (r0 + n) mod npairs (forward) or (r0 - 1 - n) mod npairs
+// (reverse), pair u and iteration it.  Forward: pairs in list order from r0,
+// it ascending; reverse: the exact reverse of that sequence.  Every pair has
+// an even length.
 struct Cursor {
-    int i, u, it;
+    int n, i, u, it;
 };
 
-__device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, bool rev) {
-    c.i = rev ? npairs - 1 : 0;
-    c.u = wave_pair(w, c.i);
+__device__ __forceinline__ void cursor_set(Cursor &c, int w, int npairs, int r0, bool rev) {
+    int i = rev ? r0 - 1 - c.n : r0 + c.n;
+    i %= npairs;
+    if (i < 0) i += npairs;
+    c.i = i;
+    c.u = wave_pair(w, i);
     c.it = rev ? 2 * c.u + 1 : 0;
 }
 
+__device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, int r0, bool rev) {
+    c.n = 0;
+    cursor_set(c, w, npairs, r0, rev);
+}
+
 // Advances; returns true when the iteration just left closed its pair.
-__device__ __forceinline__ bool cursor_next(Cursor &c, int w, bool rev) {
+__device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0, bool rev) {
     if (!rev) {
-        if (++c.it > 2 * c.u + 1) {
-            ++c.i;
-            c.u = wave_pair(w, c.i);
-            c.it = 0;
-            return true;
-        }
+        if (++c.it <= 2 * c.u + 1) return false;
     } else {
-        if (--c.it < 0) {
-            --c.i;
-            c.u = wave_pair(w, c.i);
-            c.it = 2 * c.u + 1;
-            return true;
-        }
+        if (--c.it >= 0) return false;
     }
-    return false;
+    ++c.n;
+    cursor_set(c, w, npairs, r0, rev);
+    return true;
 }
 
 __device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (c.u + 1) + c.it); }
 
+
+template <int PREC>
+__host__ __device__ constexpr int staged_slots(int Mpad);
 
 template <int PREC, int G>
 struct Shapes {
@@ -195,39 +200,64 @@ struct Shapes {
 // Dynamic LDS layout: [G k-operand groups][zs: Mpad float4][alpha: Mpad float]
 template <int PREC, int G>
 __host__ __device__ constexpr size_t dyn_lds_bytes(int Mpad) {
-    return G * kgroup_bytes<PREC>(Mpad) + (size_t)Mpad * 20;
+    return G * kgroup_bytes<PREC>(Mpad) + (size_t)staged_slots<PREC>(Mpad) * 16;
 }
 
 // One GP output for the B samples of the block; called by all threads.
 // Returns the sample's GP mean and predictive variance.
-// Inputs (zs, alpha) of output o held in registers between their global load
-// and their store to LDS: thread t owns float4 slots t, t + 256, ... of the
-// Mpad zs entries followed by the Mpad / 4 alpha quads (at most 1280 slots).
+// Per-point inputs of output o staged in LDS (float4 slots):
+//   FP32:        zs [Mpad] then alpha [Mpad / 4]            (20 B per point)
+//   BF16 forms:  2 zs [Mpad] then (c2 - |zs|^2, alpha) [Mpad / 2]  (24 B per point)
+// held in registers between their global load and their store to LDS; thread
+// t owns slots t, t + 256, ... (at most 1536 slots for Mpad <= 1024).
+template <int PREC>
+__host__ __device__ constexpr int staged_slots(int Mpad) {
+    return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : Mpad + (Mpad >> 1);
+}
+
 struct StagedInputs {
-    float4 v[5];
+    float4 v[6];
 };
 
+template <int PREC>
 __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
-    const int Mpad = g.Mpad, nz = Mpad, na = Mpad >> 2;
-    const float4 *zsrc = reinterpret_cast<const float4 *>(g.zs) + (size_t)o * Mpad;
-    const float4 *asrc = reinterpret_cast<const float4 *>(g.alpha + (size_t)o * Mpad);
+    const int Mpad = g.Mpad, nz = Mpad, ns = staged_slots<PREC>(Mpad);
+    const float4 *zsrc, *asrc;
+    if constexpr (PREC == GPMPPI_FP32) {
+        zsrc = reinterpret_cast<const float4 *>(g.zs) + (size_t)o * Mpad;
+        asrc = reinterpret_cast<const float4 *>(g.alpha + (size_t)o * Mpad);
+    } else {
+        zsrc = reinterpret_cast<const float4 *>(g.zs2) + (size_t)o * Mpad;
+        asrc = reinterpret_cast<const float4 *>(g.cza + (size_t)o * Mpad * 2);
+    }
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < 6; ++r) {
         const int slot = threadIdx.x + r * kThreads;
         if (slot < nz) st.v[r] = zsrc[slot];
-        else if (slot < nz + na) st.v[r] = asrc[slot - nz];
+        else if (slot < ns) st.v[r] = asrc[slot - nz];
     }
 }
 
+template <int PREC>
 __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev &g, unsigned char *lds,
                                             size_t zs_off) {
-    const int Mpad = g.Mpad;
+    const int ns = staged_slots<PREC>(g.Mpad);
     float4 *dst = reinterpret_cast<float4 *>(lds + zs_off);
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < 6; ++r) {
         const int slot = threadIdx.x + r * kThreads;
-        if (slot < Mpad + (Mpad >> 2)) dst[slot] = st.v[r];
+        if (slot < ns) dst[slot] = st.v[r];
     }
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f x = {a, b};
+    const v2bf h = __builtin_convertvector(x, v2bf);   // round to nearest even
+    uint32_t r;
+    __builtin_memcpy(&r, &h, 4);
+    return r;
 }
 
 // One GP output for the B samples of the block; called by all threads with
@@ -236,64 +266,87 @@ __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev 
 // next use).  Returns the sample's GP mean and predictive variance.
 template <int PREC, int G>
 __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
-                                          bool rev, unsigned char *lds, float *pred, float *vred,
-                                          float &mean_out, float &var_out) {
+                                          bool rev, int rotate, int blk, unsigned char *lds, float *pred,
+                                          float *vred, float &mean_out, float &var_out) {
     using S = Shapes<PREC, G>;
     const int Mpad = g.Mpad;
     const int nchunk = Mpad >> 3;
     const float4 *zs = reinterpret_cast<const float4 *>(lds + G * kgroup_bytes<PREC>(Mpad));
-    const float *al = reinterpret_cast<const float *>(zs + Mpad);
-    const float c2 = g.c2[o];
     const int grp = sl >> 5, s32 = sl & 31;
     unsigned char *kg = lds + grp * kgroup_bytes<PREC>(Mpad);
     float msum = 0.0f;
-    for (int c = part; c < nchunk; c += S::parts) {
-        float kv[8];
+    if constexpr (PREC == GPMPPI_FP32) {
+        // exact differences: k = exp2(c2 - sum_d (q_d - zs_d)^2)
+        const float *al = reinterpret_cast<const float *>(zs + Mpad);
+        const float c2 = g.c2[o];
+        for (int c = part; c < nchunk; c += S::parts) {
+            float kv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float4 z = zs[8 * c + e];
-            const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
-            float acc = c2;
-            acc = fmaf(-d0, d0, acc);
-            acc = fmaf(-d1, d1, acc);
-            acc = fmaf(-d2, d2, acc);
-            acc = fmaf(-d3, d3, acc);
-            kv[e] = __builtin_amdgcn_exp2f(acc);
-        }
-        const float4 a0 = *reinterpret_cast<const float4 *>(al + 8 * c);
-        const float4 a1 = *reinterpret_cast<const float4 *>(al + 8 * c + 4);
-        msum = fmaf(kv[0], a0.x, msum);
-        msum = fmaf(kv[1], a0.y, msum);
-        msum = fmaf(kv[2], a0.z, msum);
-        msum = fmaf(kv[3], a0.w, msum);
-        msum = fmaf(kv[4], a1.x, msum);
-        msum = fmaf(kv[5], a1.y, msum);
-        msum = fmaf(kv[6], a1.z, msum);
-        msum = fmaf(kv[7], a1.w, msum);
-        if constexpr (PREC == GPMPPI_FP32) {
+            for (int e = 0; e < 8; ++e) {
+                const float4 z = zs[8 * c + e];
+                const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
+                float acc = c2;
+                acc = fmaf(-d0, d0, acc);
+                acc = fmaf(-d1, d1, acc);
+                acc = fmaf(-d2, d2, acc);
+                acc = fmaf(-d3, d3, acc);
+                kv[e] = __builtin_amdgcn_exp2f(acc);
+            }
+            const float4 a0 = *reinterpret_cast<const float4 *>(al + 8 * c);
+            const float4 a1 = *reinterpret_cast<const float4 *>(al + 8 * c + 4);
+            msum = fmaf(kv[0], a0.x, msum);
+            msum = fmaf(kv[1], a0.y, msum);
+            msum = fmaf(kv[2], a0.z, msum);
+            msum = fmaf(kv[3], a0.w, msum);
+            msum = fmaf(kv[4], a1.x, msum);
+            msum = fmaf(kv[5], a1.y, msum);
+            msum = fmaf(kv[6], a1.z, msum);
+            msum = fmaf(kv[7], a1.w, msum);
             float4 *K = reinterpret_cast<float4 *>(kg) + (size_t)c * 64;
             K[s32] = make_float4(kv[0], kv[2], kv[4], kv[6]);
             K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
-        } else {
-            uint16_t hb[8];
+        }
+    } else {
+        // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs); its FP32 rounding
+        // (~1e-6 relative in k) is far below the BF16 operand rounding (2^-9)
+        const float4 *cza = zs + Mpad;   // (c2 - |zs|^2, alpha) pairs
+        const float qq = qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3];
+        for (int c = part; c < nchunk; c += S::parts) {
+            float kv[8];
+            float al8[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) hb[e] = bf16_rne(kv[e]);
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const float4 ca = cza[4 * c + e2];
+                al8[2 * e2] = ca.y;
+                al8[2 * e2 + 1] = ca.w;
+                const float cz[2] = {ca.x, ca.z};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = 2 * e2 + h;
+                    const float4 z2 = zs[8 * c + e];
+                    float acc = cz[h] - qq;
+                    acc = fmaf(qs[0], z2.x, acc);
+                    acc = fmaf(qs[1], z2.y, acc);
+                    acc = fmaf(qs[2], z2.z, acc);
+                    acc = fmaf(qs[3], z2.w, acc);
+                    kv[e] = __builtin_amdgcn_exp2f(fminf(acc, 64.0f));
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) msum = fmaf(kv[e], al8[e], msum);
             uint4 hv;
-            hv.x = (uint32_t)hb[0] | ((uint32_t)hb[1] << 16);
-            hv.y = (uint32_t)hb[2] | ((uint32_t)hb[3] << 16);
-            hv.z = (uint32_t)hb[4] | ((uint32_t)hb[5] << 16);
-            hv.w = (uint32_t)hb[6] | ((uint32_t)hb[7] << 16);
+            hv.x = pack_bf16x2(kv[0], kv[1]);
+            hv.y = pack_bf16x2(kv[2], kv[3]);
+            hv.z = pack_bf16x2(kv[4], kv[5]);
+            hv.w = pack_bf16x2(kv[6], kv[7]);
             const int idx = (c >> 1) * 64 + s32 + 32 * (c & 1);
             reinterpret_cast<uint4 *>(kg)[idx] = hv;
             if constexpr (PREC == GPMPPI_BF16X3) {
-                uint16_t lb[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) lb[e] = bf16_rne(kv[e] - bf16_to_f32(hb[e]));
                 uint4 lv;
-                lv.x = (uint32_t)lb[0] | ((uint32_t)lb[1] << 16);
-                lv.y = (uint32_t)lb[2] | ((uint32_t)lb[3] << 16);
-                lv.z = (uint32_t)lb[4] | ((uint32_t)lb[5] << 16);
-                lv.w = (uint32_t)lb[6] | ((uint32_t)lb[7] << 16);
+                lv.x = pack_bf16x2(kv[0] - bf16_to_f32((uint16_t)hv.x), kv[1] - bf16_to_f32((uint16_t)(hv.x >> 16)));
+                lv.y = pack_bf16x2(kv[2] - bf16_to_f32((uint16_t)hv.y), kv[3] - bf16_to_f32((uint16_t)(hv.y >> 16)));
+                lv.z = pack_bf16x2(kv[4] - bf16_to_f32((uint16_t)hv.z), kv[5] - bf16_to_f32((uint16_t)(hv.z >> 16)));
+                lv.w = pack_bf16x2(kv[6] - bf16_to_f32((uint16_t)hv.w), kv[7] - bf16_to_f32((uint16_t)(hv.w >> 16)));
                 reinterpret_cast<uint4 *>(kg + (size_t)Mpad * 64)[idx] = lv;
             }
         }
@@ -302,7 +355,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     pred[part * S::B + sl] = msum;
     __syncthreads();
     StagedInputs st;
-    if (next_o >= 0) stage_load(st, g, next_o);
+    if (next_o >= 0) stage_load<PREC>(st, g, next_o);
 
     // ---- variance contraction on the matrix cores
     const int lane = threadIdx.x & 63;
@@ -313,6 +366,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     if (wave_pair(w, rounds - 1) >= NP) npairs = rounds - 1;
     int nit = 0;
     for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair(w, i) + 2;   // even
+    const int r0 = (rotate && npairs > 0) ? (int)((unsigned)blk % (unsigned)npairs) : 0;
 
     const unsigned char *kgrp[G];
 #pragma unroll
@@ -330,14 +384,14 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     }
     Cursor pc, mc;   // prefetch and compute cursors
     if (nit > 0) {
-        cursor_start(pc, w, npairs, rev);
-        cursor_start(mc, w, npairs, rev);
+        cursor_start(pc, w, npairs, r0, rev);
+        cursor_start(mc, w, npairs, r0, rev);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int b0 = pair_block(pc);
             load_wblock<PREC>(ring[r][0], g, o, b0, lane);
             load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-            cursor_next(pc, w, rev);
+            cursor_next(pc, w, npairs, r0, rev);
         }
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
@@ -350,12 +404,12 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                 const int b0 = pair_block(pc);
                 load_wblock<PREC>(ring[r][0], g, o, b0, lane);
                 load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-                cursor_next(pc, w, rev);
+                cursor_next(pc, w, npairs, r0, rev);
             }
             KOp<PREC> kuse[G];
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) kuse[gg] = kcur[gg];
-            const bool pair_end = cursor_next(mc, w, rev);
+            const bool pair_end = cursor_next(mc, w, npairs, r0, rev);
             if (base + r + 1 < nit) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
@@ -385,7 +439,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
     }
     __syncthreads();
-    if (next_o >= 0) stage_store(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
+    if (next_o >= 0) stage_store<PREC>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
     float v2 = 0.0f, m = 0.0f;
 #pragma unroll
     for (int ww = 0; ww < kWaves; ++ww) v2 += vred[ww * S::B + sl];
@@ -395,19 +449,18 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     mean_out = m;
 }
 
+// The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
+// problem; called by all threads of a workgroup.
 template <int PREC, int G>
-__global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
+__device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, unsigned char *lds, float *pred,
+                                              float *ored, float *vred) {
     using S = Shapes<PREC, G>;
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float pred[S::parts * S::B];
-    __shared__ float ored[S::parts * S::B];
-    __shared__ float vred[kWaves * S::B];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int sl = lane % S::B;                     // sample within the block
     const int part = (G == 2) ? w : 2 * w + (lane >> 5);
     const int wu = __builtin_amdgcn_readfirstlane(w);   // wave-uniform loop splitter for G = 2
-    const int sg = blockIdx.x * S::B + sl;
+    const int sg = blk * S::B + sl;
     const bool valid = sg < a.K;
     const bool writer = valid && w == 0 && lane < S::B;
     const int K = a.K;
@@ -445,8 +498,8 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
 
     {   // inputs of output 0 (the first output of step 0)
         StagedInputs st;
-        stage_load(st, a.gp, 0);
-        stage_store(st, a.gp, lds, zs_off);
+        stage_load<PREC>(st, a.gp, 0);
+        stage_store<PREC>(st, a.gp, lds, zs_off);
     }
     for (int k = 0; k < a.T; ++k) {
         // even steps: outputs 0 then 1; odd steps: 1 then 0 (and blocks reversed)
@@ -460,7 +513,8 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
             __syncthreads();   // staged inputs visible; previous k-operand readers are done
             const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
                                  q[3] * a.gp.scale[o][3]};
-            gp_output<PREC, G>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, lds, pred, vred, m[o], s2[o]);
+            gp_output<PREC, G>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
+                               m[o], s2[o]);
         }
 
         // ---- mean: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2, 10)
@@ -597,6 +651,42 @@ __global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
 }
 
 template <int PREC, int G>
+__global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
+    using S = Shapes<PREC, G>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ float pred[S::parts * S::B];
+    __shared__ float ored[S::parts * S::B];
+    __shared__ float vred[kWaves * S::B];
+    rollout_block<PREC, G>(a, blockIdx.x, lds, pred, ored, vred);
+}
+
+// Persistent rollout of many independent problems: every workgroup takes
+// (problem, sample block) items from a shared counter until the list (sorted
+// longest first) is exhausted.  Results do not depend on which workgroup
+// runs an item.  *counter must be 0 at launch.
+template <int PREC, int G>
+__global__ __launch_bounds__(kThreads) void rollout_batch_kernel(const RolloutArgs *probs, const int2 *items,
+                                                                 int n_items, uint32_t *counter) {
+    using S = Shapes<PREC, G>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ float pred[S::parts * S::B];
+    __shared__ float ored[S::parts * S::B];
+    __shared__ float vred[kWaves * S::B];
+    __shared__ int next_item;
+    for (;;) {
+        __syncthreads();   // every thread has read the previous item
+        if (threadIdx.x == 0) next_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(next_item);
+        if (it >= n_items) break;
+        const int2 pb = items[it];
+        const int p = __builtin_amdgcn_readfirstlane(pb.x);
+        const int b = __builtin_amdgcn_readfirstlane(pb.y);
+        rollout_block<PREC, G>(probs[p], b, lds, pred, ored, vred);
+    }
+}
+
+template <int PREC, int G>
 __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const float *q, int n, float *mean,
                                                               float *var) {
     using S = Shapes<PREC, G>;
@@ -614,8 +704,8 @@ __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const flo
     const size_t zs_off = G * kgroup_bytes<PREC>(g.Mpad);
     {
         StagedInputs st;
-        stage_load(st, g, 0);
-        stage_store(st, g, lds, zs_off);
+        stage_load<PREC>(st, g, 0);
+        stage_store<PREC>(st, g, lds, zs_off);
     }
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
@@ -623,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const flo
         const float qs[4] = {qv[0] * g.scale[o][0], qv[1] * g.scale[o][1], qv[2] * g.scale[o][2],
                              qv[3] * g.scale[o][3]};
         float m, s2;
-        gp_output<PREC, G>(g, o, o == 0 ? 1 : -1, qs, part, sl, false, lds, pred, vred, m, s2);
+        gp_output<PREC, G>(g, o, o == 0 ? 1 : -1, qs, part, sl, false, 0, blockIdx.x, lds, pred, vred, m, s2);
         if (sg < n && w == 0 && lane < S::B) {
             mean[(size_t)o * n + sg] = m;
             var[(size_t)o * n + sg] = s2;
@@ -653,8 +743,6 @@ size_t rollout_lds_bytes(int precision, int Mpad) {
     }
 }
 
-int rollout_samples_per_block(int precision, int Mpad) { return 32 * groups_for(precision, Mpad); }
-
 template <typename F>
 static hipError_t set_lds(F *fn, size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
@@ -669,6 +757,34 @@ static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
     const dim3 grid((a.K + 32 * G - 1) / (32 * G));
     hipLaunchKernelGGL((rollout_kernel<PREC, G>), grid, dim3(kThreads), lds, st, a);
     return hipGetLastError();
+}
+
+template <int PREC, int G>
+static hipError_t launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items, uint32_t *counter,
+                                         int Mpad_max, int grid, hipStream_t st) {
+    const size_t lds = dyn_lds_bytes<PREC, G>(Mpad_max);
+    hipError_t e = set_lds(rollout_batch_kernel<PREC, G>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rollout_batch_kernel<PREC, G>), dim3(grid), dim3(kThreads), lds, st, probs, items, n_items,
+                       counter);
+    return hipGetLastError();
+}
+
+int rollout_groups(int precision, int Mpad) { return groups_for(precision, Mpad); }
+
+hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
+                                int precision, int G, int Mpad_max, int grid, hipStream_t st) {
+    switch (precision) {
+        case GPMPPI_FP32:
+            return G == 2 ? launch_rollout_batch_t<GPMPPI_FP32, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
+                          : launch_rollout_batch_t<GPMPPI_FP32, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+        case GPMPPI_BF16:
+            return G == 2 ? launch_rollout_batch_t<GPMPPI_BF16, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
+                          : launch_rollout_batch_t<GPMPPI_BF16, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+        default:
+            return G == 2 ? launch_rollout_batch_t<GPMPPI_BF16X3, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
+                          : launch_rollout_batch_t<GPMPPI_BF16X3, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+    }
 }
 
 hipError_t launch_rollout(const RolloutArgs &a, int precision, hipStream_t st) {

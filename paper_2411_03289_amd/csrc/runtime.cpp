@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -74,7 +76,8 @@ struct gpmppi_ctx {
     int M = 0, Mpad = 0, NT = 0;
     double z_p = 0, c_p = 0;
     // device buffers
-    float *zs = nullptr, *alpha = nullptr;
+    float *zs = nullptr, *alpha = nullptr, *zs2 = nullptr, *cza = nullptr;
+    int rotate = 1;
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
     long long w32_stride = 0, wb_stride = 0;
@@ -192,7 +195,9 @@ gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
         uint32_t notpd = 0;
         HIP_TRY(hipMemcpy(&notpd, c->flags + 1, sizeof notpd, hipMemcpyDeviceToHost));
         if (notpd) return fail(GPMPPI_E_NOT_PD, "GP %d: K(Z,Z) + sn^2 I is not positive definite", o);
-        HIP_TRY(pack_gp_output(b, M, Mpad, scale, c->zs + (size_t)o * Mpad * 4, c->alpha + (size_t)o * Mpad,
+        const double c2 = 2.0 * gp[o].log_sf / std::log(2.0);
+        HIP_TRY(pack_gp_output(b, M, Mpad, scale, c2, c->zs + (size_t)o * Mpad * 4, c->alpha + (size_t)o * Mpad,
+                               c->zs2 + (size_t)o * Mpad * 4, c->cza + (size_t)o * Mpad * 2,
                                c->w32 + o * c->w32_stride, c->wbh + o * c->wb_stride, c->wbl + o * c->wb_stride,
                                nullptr));
         HIP_TRY(hipDeviceSynchronize());
@@ -228,6 +233,7 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     a.step_counter = step_counter;
     a.K = c->params.K;
     a.T = c->params.T;
+    a.rotate = c->rotate;
     a.x0 = x0;
     a.U = U;
     a.costs = costs;
@@ -291,6 +297,8 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     };
     c->zs = track(dev_alloc<float>((size_t)2 * Mpad * 4, st));
     c->alpha = track(dev_alloc<float>((size_t)2 * Mpad, st));
+    c->zs2 = track(dev_alloc<float>((size_t)2 * Mpad * 4, st));
+    c->cza = track(dev_alloc<float>((size_t)2 * Mpad * 2, st));
     c->w32 = track(dev_alloc<float4>((size_t)2 * c->w32_stride, st));
     c->wbh = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
     c->wbl = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
@@ -340,6 +348,9 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
 
     c->gp.zs = c->zs;
     c->gp.alpha = c->alpha;
+    c->gp.zs2 = c->zs2;
+    c->gp.cza = c->cza;
+    if (const char *r = std::getenv("GPMPPI_ROTATE")) c->rotate = std::atoi(r);
     c->gp.w32 = c->w32;
     c->gp.wbh = c->wbh;
     c->gp.wbl = c->wbl;
@@ -512,6 +523,226 @@ gpmppi_status gpmppi_info(const gpmppi_ctx *c, int32_t *M_pad, double *z_p, doub
     if (c_p) *c_p = c->c_p;
     return GPMPPI_OK;
 }
+
+// ------------------------------------------------------------------ batch
+}  // extern "C"
+
+struct gpmppi_batch {
+    int n = 0, precision = 0, G = 2, Mpad_max = 0, grid = 0;
+    std::vector<gpmppi_ctx *> ctx;
+    std::vector<long long> U_off, K_off;   // n + 1 each
+    int n_items = 0, n_upd = 0;
+    RolloutArgs *ra = nullptr;      // [n] device
+    UpdateArgs *ua = nullptr;       // [n] device
+    int2 *items = nullptr;          // rollout items (problem, block), longest first
+    int2 *upd_items = nullptr;      // update items (problem, step)
+    long long *U_off_d = nullptr, *K_off_d = nullptr;
+    int *T_d = nullptr;
+    Dyn *dyn_d = nullptr;
+    uint32_t *counters = nullptr;   // [0] work counter, [1] closed-loop step
+    float *cost_scratch = nullptr;
+    std::vector<void *> owned;
+    ~gpmppi_batch() {
+        for (void *p : owned) (void)hipFree(p);
+        for (gpmppi_ctx *c : ctx) delete c;
+    }
+};
+
+namespace {
+
+gpmppi_status batch_enqueue_step(gpmppi_batch *b, hipStream_t st) {
+    HIP_TRY(launch_counter_reset(b->counters, st));
+    HIP_TRY(launch_rollout_batch(b->ra, b->items, b->n_items, b->counters, b->precision, b->G, b->Mpad_max,
+                                 b->grid, st));
+    HIP_TRY(launch_update_batch(b->ua, b->upd_items, b->n_upd, st));
+    return GPMPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const gpmppi_gp gp[],
+                                const gpmppi_obstacles obstacles[], const gpmppi_path paths[], gpmppi_batch **out) {
+    g_last_error.clear();
+    if (!out || !params || !gp || !obstacles || !paths) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n < 1 || n > 4096) return fail(GPMPPI_E_INVALID, "problem count must lie in [1, 4096]");
+    for (int p = 0; p < n; ++p) {
+        gpmppi_status st;
+        if ((st = validate_params(&params[p])) != GPMPPI_OK) return st;
+        if (params[p].precision != params[0].precision)
+            return fail(GPMPPI_E_INVALID, "all problems of a batch need the same precision");
+        if ((st = validate_gp(&gp[2 * p])) != GPMPPI_OK) return st;
+        if ((st = validate_world(&obstacles[p], &paths[p])) != GPMPPI_OK) return st;
+    }
+    auto *b = new gpmppi_batch();
+    b->n = n;
+    b->precision = params[0].precision;
+    b->U_off.assign(n + 1, 0);
+    b->K_off.assign(n + 1, 0);
+    for (int p = 0; p < n; ++p) {
+        gpmppi_ctx *c = nullptr;
+        gpmppi_status st = gpmppi_init(&params[p], &gp[2 * p], &obstacles[p], &paths[p], &c);
+        if (st != GPMPPI_OK) {
+            delete b;
+            return st;
+        }
+        b->ctx.push_back(c);
+        b->U_off[p + 1] = b->U_off[p] + 2LL * params[p].T;
+        b->K_off[p + 1] = b->K_off[p] + params[p].K;
+        b->Mpad_max = std::max(b->Mpad_max, c->Mpad);
+    }
+    b->G = 2;
+    for (gpmppi_ctx *c : b->ctx) b->G = std::min(b->G, rollout_groups(b->precision, c->Mpad));
+    b->G = std::min(b->G, rollout_groups(b->precision, b->Mpad_max));
+    const int B = 32 * b->G;
+    // items: (problem, sample block), longest first (estimated cost)
+    std::vector<std::pair<double, int2>> it;
+    std::vector<int2> upd;
+    for (int p = 0; p < n; ++p) {
+        const gpmppi_ctx *c = b->ctx[p];
+        const double cost = (double)params[p].T * ((double)c->Mpad * c->Mpad + 16.0 * c->Mpad +
+                                                    (double)c->geo.P + 2.0 * c->n_obs + 200.0);
+        for (int blk = 0; blk < (params[p].K + B - 1) / B; ++blk) it.push_back({cost, make_int2(p, blk)});
+        for (int k = 0; k < params[p].T; ++k) upd.push_back(make_int2(p, k));
+    }
+    std::stable_sort(it.begin(), it.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+    std::vector<int2> items;
+    for (auto &e : it) items.push_back(e.second);
+    b->n_items = (int)items.size();
+    b->n_upd = (int)upd.size();
+    std::vector<RolloutArgs> ra(n);
+    std::vector<UpdateArgs> ua(n);
+    std::vector<int> T(n);
+    std::vector<Dyn> dyn(n);
+    for (int p = 0; p < n; ++p) {
+        ra[p] = rollout_args(b->ctx[p], nullptr, nullptr, 0, nullptr, nullptr, nullptr);
+        ua[p] = update_args(b->ctx[p], nullptr, nullptr, 0, nullptr, nullptr, nullptr);
+        T[p] = params[p].T;
+        dyn[p] = b->ctx[p]->dyn;
+    }
+    gpmppi_status st = GPMPPI_OK;
+    auto track = [&](auto *p) {
+        if (p) b->owned.push_back((void *)p);
+        return p;
+    };
+    b->ra = track(dev_alloc<RolloutArgs>(n, st));
+    b->ua = track(dev_alloc<UpdateArgs>(n, st));
+    b->items = track(dev_alloc<int2>(items.size(), st));
+    b->upd_items = track(dev_alloc<int2>(upd.size(), st));
+    b->U_off_d = track(dev_alloc<long long>(n + 1, st));
+    b->K_off_d = track(dev_alloc<long long>(n + 1, st));
+    b->T_d = track(dev_alloc<int>(n, st));
+    b->dyn_d = track(dev_alloc<Dyn>(n, st));
+    b->counters = track(dev_alloc<uint32_t>(4, st));
+    b->cost_scratch = track(dev_alloc<float>((size_t)b->K_off[n], st));
+    if (st != GPMPPI_OK) {
+        delete b;
+        return st;
+    }
+#define UP(dst, src, bytes)                                                                   \
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {                    \
+        delete b;                                                                             \
+        return fail(GPMPPI_E_HIP, "upload of the batch tables failed");                       \
+    }
+    UP(b->ra, ra.data(), sizeof(RolloutArgs) * n);
+    UP(b->ua, ua.data(), sizeof(UpdateArgs) * n);
+    UP(b->items, items.data(), sizeof(int2) * items.size());
+    UP(b->upd_items, upd.data(), sizeof(int2) * upd.size());
+    UP(b->U_off_d, b->U_off.data(), sizeof(long long) * (n + 1));
+    UP(b->K_off_d, b->K_off.data(), sizeof(long long) * (n + 1));
+    UP(b->T_d, T.data(), sizeof(int) * n);
+    UP(b->dyn_d, dyn.data(), sizeof(Dyn) * n);
+#undef UP
+    if (hipMemset(b->counters, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+        delete b;
+        return fail(GPMPPI_E_HIP, "hipMemset failed");
+    }
+    // persistent grid: every CU times the workgroups it can hold at this LDS size
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t lds = rollout_lds_bytes(b->precision, b->Mpad_max);
+    const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / (lds + 4096))));
+    b->grid = std::max(1, std::min(b->n_items, std::max(1, cus) * per_cu));
+    *out = b;
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_batch_layout(const gpmppi_batch *b, int64_t *U_off, int64_t *K_off) {
+    g_last_error.clear();
+    if (!b) return fail(GPMPPI_E_INVALID, "batch is NULL");
+    for (int p = 0; p <= b->n; ++p) {
+        if (U_off) U_off[p] = b->U_off[p];
+        if (K_off) K_off[p] = b->K_off[p];
+    }
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_batch_step(gpmppi_batch *b, const float *x0_d, const float *U_d, uint64_t seed, float *U_out_d,
+                                float *costs_d, float *weights_d, void *stream) {
+    g_last_error.clear();
+    if (!b || !x0_d || !U_d || !U_out_d || !costs_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const BatchPtrs q{x0_d, U_d, U_out_d, costs_d, weights_d, seed, nullptr, b->U_off_d, b->K_off_d};
+    HIP_TRY(launch_batch_patch(b->ra, b->ua, b->n, q, st));
+    return batch_enqueue_step(b, st);
+}
+
+gpmppi_status gpmppi_batch_closed_loop(gpmppi_batch *b, float *x_d, float *U_d, uint64_t seed0, int32_t n_steps,
+                                       double amplitude, float *x_hist_d, int32_t use_graph, void *stream) {
+    g_last_error.clear();
+    if (!b || !x_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n_steps < 0) return fail(GPMPPI_E_INVALID, "n_steps must be >= 0");
+    if (!is_fin(amplitude)) return fail(GPMPPI_E_NONFINITE, "non-finite plant amplitude");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *step = b->counters + 1;
+    HIP_TRY(launch_counter_reset(step, st));
+    if (x_hist_d) HIP_TRY(hipMemcpyAsync(x_hist_d, x_d, sizeof(float) * 5 * b->n, hipMemcpyDeviceToDevice, st));
+    const BatchPtrs q{x_d, U_d, U_d, b->cost_scratch, nullptr, seed0, step, b->U_off_d, b->K_off_d};
+    HIP_TRY(launch_batch_patch(b->ra, b->ua, b->n, q, st));
+    if (n_steps == 0) return GPMPPI_OK;
+    auto enqueue = [&](hipStream_t s) -> gpmppi_status {
+        gpmppi_status r = batch_enqueue_step(b, s);
+        if (r != GPMPPI_OK) return r;
+        HIP_TRY(launch_plant_shift_batch(x_d, U_d, b->U_off_d, b->T_d, b->dyn_d, (float)amplitude, step, x_hist_d,
+                                         b->n, s));
+        HIP_TRY(launch_counter_add(step, 1u, s));
+        return GPMPPI_OK;
+    };
+    if (!use_graph) {
+        for (int t = 0; t < n_steps; ++t) {
+            gpmppi_status r = enqueue(st);
+            if (r != GPMPPI_OK) return r;
+        }
+        return GPMPPI_OK;
+    }
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipEvent_t ready;
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ready, st));
+    HIP_TRY(hipStreamWaitEvent(cap, ready, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    gpmppi_status r = enqueue(cap);
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (r != GPMPPI_OK) return r;
+    if (ce != hipSuccess) return fail(GPMPPI_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (int t = 0; t < n_steps; ++t) HIP_TRY(hipGraphLaunch(exec, cap));
+    HIP_TRY(hipEventRecord(ready, cap));
+    HIP_TRY(hipStreamWaitEvent(st, ready, 0));
+    HIP_TRY(hipStreamSynchronize(cap));
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ready);
+    (void)hipStreamDestroy(cap);
+    return GPMPPI_OK;
+}
+
+void gpmppi_batch_destroy(gpmppi_batch *b) { delete b; }
 
 double gpmppi_norm_quantile(double p) {
     if (!(p > 0.0 && p < 1.0)) return std::nan("");

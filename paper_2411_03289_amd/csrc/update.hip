@@ -47,9 +47,8 @@ __device__ __forceinline__ void block_sum3(float &a, float &b, float &c, float *
 // Block k computes U'_k = sum_s w^s u_k^s with w^s = exp(-(S^s - rho)/lambda) / Z,
 // rho = min S.  Every block evaluates the same fixed-order min and sum, so the
 // normaliser is identical everywhere; block 0 also writes the weights.
-__global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
-    __shared__ float sh[3 * kUpdThreads / 64];
-    const int tid = threadIdx.x, k = blockIdx.x;
+__device__ __forceinline__ void update_step(const UpdateArgs &a, int k, float *sh) {
+    const int tid = threadIdx.x;
     NoiseParams np = a.noise;
     {
         uint64_t seed = a.seed;
@@ -88,6 +87,25 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
     }
 }
 
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
+    __shared__ float sh[3 * kUpdThreads / 64];
+    update_step(a, blockIdx.x, sh);
+}
+
+// One workgroup per (problem, horizon step) item of a batch.
+__global__ __launch_bounds__(kUpdThreads) void update_batch_kernel(const UpdateArgs *probs, const int2 *items) {
+    __shared__ float sh[3 * kUpdThreads / 64];
+    const int2 pk = items[blockIdx.x];
+    const int p = __builtin_amdgcn_readfirstlane(pk.x);
+    const int k = __builtin_amdgcn_readfirstlane(pk.y);
+    update_step(probs[p], k, sh);
+}
+
+hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st) {
+    hipLaunchKernelGGL(update_batch_kernel, dim3(n_items), dim3(kUpdThreads), 0, st, probs_d, items_d);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(update_kernel, dim3(a.T), dim3(kUpdThreads), 0, st, a);
     return hipGetLastError();
@@ -108,10 +126,9 @@ hipError_t launch_philox(uint64_t seed, const uint32_t *ctr, int n, uint32_t *ou
 // Synthetic plant (nominal Euler step plus amplitude * sin(v w) on both
 // velocity derivatives) driven by U_0, then the warm-start shift
 // U <- [U_1 .. U_{T-1}, U_{T-1}].  One block; T <= 4096.
-__global__ __launch_bounds__(256) void plant_shift_kernel(const float *x, float *x_out, float *U, int T, Dyn dy,
-                                                          float amp, uint32_t *step_counter, float *x_hist,
-                                                          float *U0_hist) {
-    __shared__ float xs[5];
+__device__ __forceinline__ void plant_shift_body(const float *x, float *x_out, float *U, int T, Dyn dy, float amp,
+                                                 const uint32_t *step_counter, float *x_hist, float *U0_hist,
+                                                 float *xs) {
     const int tid = threadIdx.x;
     const uint32_t t = step_counter ? *step_counter : 0u;
     if (tid == 0) {
@@ -144,8 +161,69 @@ __global__ __launch_bounds__(256) void plant_shift_kernel(const float *x, float 
         x_out[tid] = xs[tid];
         if (x_hist) x_hist[(size_t)(t + 1) * 5 + tid] = xs[tid];
     }
+}
+
+__global__ __launch_bounds__(256) void plant_shift_kernel(const float *x, float *x_out, float *U, int T, Dyn dy,
+                                                          float amp, uint32_t *step_counter, float *x_hist,
+                                                          float *U0_hist) {
+    __shared__ float xs[5];
+    plant_shift_body(x, x_out, U, T, dy, amp, step_counter, x_hist, U0_hist, xs);
     __syncthreads();
-    if (tid == 0 && step_counter) *step_counter = t + 1;
+    if (threadIdx.x == 0 && step_counter) *step_counter = *step_counter + 1;
+}
+
+// Workgroup p: plant step and shift of problem p of a batch; x [n][5], U packed
+// with offsets U_off (floats), x_hist [steps + 1][n][5].  The step counter
+// is advanced by the separate counter kernel after all problems.
+__global__ __launch_bounds__(256) void plant_shift_batch_kernel(float *x, float *U, const long long *U_off,
+                                                                const int *T, const Dyn *dyn, float amp,
+                                                                const uint32_t *step_counter, float *x_hist,
+                                                                int n) {
+    __shared__ float xs[5];
+    const int p = blockIdx.x;
+    const uint32_t t = *step_counter;
+    plant_shift_body(x + 5 * p, x + 5 * p, U + U_off[p], T[p], dyn[p], amp, nullptr, nullptr, nullptr, xs);
+    __syncthreads();
+    if (x_hist && threadIdx.x < 5) x_hist[((size_t)(t + 1) * n + p) * 5 + threadIdx.x] = x[5 * p + threadIdx.x];
+}
+
+hipError_t launch_plant_shift_batch(float *x, float *U, const long long *U_off, const int *T, const Dyn *dyn,
+                                    float amplitude, const uint32_t *step_counter, float *x_hist, int n,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(plant_shift_batch_kernel, dim3(n), dim3(256), 0, st, x, U, U_off, T, dyn, amplitude,
+                       step_counter, x_hist, n);
+    return hipGetLastError();
+}
+
+__global__ void batch_patch_kernel(RolloutArgs *ra, UpdateArgs *ua, int n, BatchPtrs q) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const long long uo = q.U_off[p], ko = q.K_off[p];
+    ra[p].x0 = q.x0 + 5 * p;
+    ra[p].U = q.U + uo;
+    ra[p].costs = q.costs + ko;
+    ra[p].seed = q.seed;
+    ra[p].step_counter = q.step_counter;
+    ua[p].U = q.U + uo;
+    ua[p].U_out = q.U_out + uo;
+    ua[p].costs = q.costs + ko;
+    ua[p].weights = q.weights ? q.weights + ko : nullptr;
+    ua[p].seed = q.seed;
+    ua[p].step_counter = q.step_counter;
+}
+
+hipError_t launch_batch_patch(RolloutArgs *ra, UpdateArgs *ua, int n, BatchPtrs ptrs, hipStream_t st) {
+    hipLaunchKernelGGL(batch_patch_kernel, dim3((n + 63) / 64), dim3(64), 0, st, ra, ua, n, ptrs);
+    return hipGetLastError();
+}
+
+__global__ void counter_add_kernel(uint32_t *c, uint32_t v) {
+    if (threadIdx.x == 0) c[0] += v;
+}
+
+hipError_t launch_counter_add(uint32_t *counter, uint32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, st, counter, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_plant_shift(const float *x, float *x_out, float *U, int T, Dyn dyn, float amplitude,

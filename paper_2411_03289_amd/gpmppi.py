@@ -86,6 +86,11 @@ def lib() -> ctypes.CDLL:
         "gpmppi_philox": [u64, vp, i32, vp, vp],
         "gpmppi_status_flags": [vp, ctypes.POINTER(ctypes.c_uint32)],
         "gpmppi_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(f64), ctypes.POINTER(f64)],
+        "gpmppi_batch_init": [i32, ctypes.POINTER(gpmppi_params), ctypes.POINTER(gpmppi_gp),
+                              ctypes.POINTER(gpmppi_obstacles), ctypes.POINTER(gpmppi_path), ctypes.POINTER(vp)],
+        "gpmppi_batch_layout": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+        "gpmppi_batch_step": [vp, vp, vp, u64, vp, vp, vp, vp],
+        "gpmppi_batch_closed_loop": [vp, vp, vp, u64, i32, f64, vp, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -93,6 +98,8 @@ def lib() -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     L.gpmppi_destroy.argtypes = [vp]
     L.gpmppi_destroy.restype = None
+    L.gpmppi_batch_destroy.argtypes = [vp]
+    L.gpmppi_batch_destroy.restype = None
     L.gpmppi_last_error.argtypes = []
     L.gpmppi_last_error.restype = ctypes.c_char_p
     L.gpmppi_norm_quantile.argtypes = [f64]
@@ -181,12 +188,9 @@ def _gp_structs(problem, keep: list):
     return gps
 
 
-def gpmppi_init(problem, precision: int = FP32) -> Context:
-    """Creates a context from a workload Problem (see workloads.Problem)."""
-    keep: list = []
-    params = make_params(problem, precision)
-    gps = _gp_structs(problem, keep)
+def _world_structs(problem, keep: list):
     ob_arr, ob_p = _as_c_double(problem.obstacles.reshape(-1, 3))
+    keep.append(ob_arr)
     obs = gpmppi_obstacles(n=problem.obstacles.shape[0], xyr=ob_p)
     if problem.path_kind == 0:
         cx, cy, R = problem.circle
@@ -196,6 +200,15 @@ def gpmppi_init(problem, precision: int = FP32) -> Context:
         keep.append(pts)
         path = gpmppi_path(kind=1, cx=0, cy=0, R=0, P=pts.shape[0], pts=pts_p,
                            half_width=problem.params["half_width"])
+    return obs, path
+
+
+def gpmppi_init(problem, precision: int = FP32) -> Context:
+    """Creates a context from a workload Problem (see workloads.Problem)."""
+    keep: list = []
+    params = make_params(problem, precision)
+    gps = _gp_structs(problem, keep)
+    obs, path = _world_structs(problem, keep)
     h = ctypes.c_void_p()
     _check(lib().gpmppi_init(ctypes.byref(params), gps, ctypes.byref(obs), ctypes.byref(path), ctypes.byref(h)))
     return Context(h.value, dict(K=problem.K, T=problem.T, M=problem.M, precision=precision))
@@ -310,3 +323,62 @@ def gpmppi_destroy(ctx: Context):
 
 def gpmppi_last_error() -> str:
     return lib().gpmppi_last_error().decode()
+
+
+class Batch:
+    """Owns a gpmppi_batch; destroyed with the object."""
+
+    def __init__(self, handle: int, problems, U_off, K_off):
+        self.handle = ctypes.c_void_p(handle)
+        self.n = len(problems)
+        self.U_off = U_off
+        self.K_off = K_off
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.gpmppi_batch_destroy(self.handle)
+            self.handle = None
+
+
+def gpmppi_batch_init(problems, precision: int = FP32) -> Batch:
+    keep: list = []
+    n = len(problems)
+    params = (gpmppi_params * n)(*[make_params(p, precision) for p in problems])
+    gps = (gpmppi_gp * (2 * n))()
+    obs = (gpmppi_obstacles * n)()
+    paths = (gpmppi_path * n)()
+    for i, p in enumerate(problems):
+        g = _gp_structs(p, keep)
+        gps[2 * i], gps[2 * i + 1] = g[0], g[1]
+        obs[i], paths[i] = _world_structs(p, keep)
+    h = ctypes.c_void_p()
+    _check(lib().gpmppi_batch_init(n, params, gps, obs, paths, ctypes.byref(h)))
+    U_off = (ctypes.c_int64 * (n + 1))()
+    K_off = (ctypes.c_int64 * (n + 1))()
+    _check(lib().gpmppi_batch_layout(h, U_off, K_off))
+    return Batch(h.value, problems, list(U_off), list(K_off))
+
+
+def gpmppi_batch_layout(b: Batch):
+    return b.U_off, b.K_off
+
+
+def gpmppi_batch_step(b: Batch, x0, U, seed: int, U_out, costs, weights=None, stream=None):
+    nU, nK = b.U_off[-1], b.K_off[-1]
+    _check(lib().gpmppi_batch_step(b.handle, _dev(x0, 5 * b.n, "x0"), _dev(U, nU, "U"), ctypes.c_uint64(seed),
+                                   _dev(U_out, nU, "U_out"), _dev(costs, nK, "costs"),
+                                   _dev(weights, nK, "weights", optional=True), _stream(stream)))
+
+
+def gpmppi_batch_closed_loop(b: Batch, x, U, seed0: int, n_steps: int, amplitude: float, x_hist=None,
+                             use_graph: bool = False, stream=None):
+    _check(lib().gpmppi_batch_closed_loop(b.handle, _dev(x, 5 * b.n, "x"), _dev(U, b.U_off[-1], "U"),
+                                          ctypes.c_uint64(seed0), int(n_steps), float(amplitude),
+                                          _dev(x_hist, 5 * b.n * (n_steps + 1), "x_hist", optional=True),
+                                          int(bool(use_graph)), _stream(stream)))
+
+
+def gpmppi_batch_destroy(b: Batch):
+    if b.handle:
+        lib().gpmppi_batch_destroy(b.handle)
+        b.handle = None

@@ -112,3 +112,23 @@ def test_null_arguments_rejected(L):
 def test_binding_names_follow_the_abi():
     for n in _declared():
         assert hasattr(B, n), n
+
+
+def test_batch_validation_without_device(L):
+    ps = [W.small_problem(seed_data=1), W.small_problem(seed_data=2)]
+    keep = []
+    params = (B.gpmppi_params * 2)(B.make_params(ps[0], B.FP32), B.make_params(ps[1], B.BF16))
+    gps = (B.gpmppi_gp * 4)()
+    obs = (B.gpmppi_obstacles * 2)()
+    paths = (B.gpmppi_path * 2)()
+    for i, p in enumerate(ps):
+        g = B._gp_structs(p, keep)
+        gps[2 * i], gps[2 * i + 1] = g[0], g[1]
+        obs[i], paths[i] = B._world_structs(p, keep)
+    h = ctypes.c_void_p()
+    assert L.gpmppi_batch_init(2, params, gps, obs, paths, ctypes.byref(h)) == -1   # mixed precision
+    assert L.gpmppi_batch_init(0, params, gps, obs, paths, ctypes.byref(h)) == -1
+    params[1].precision = B.FP32
+    params[1].K = 0
+    assert L.gpmppi_batch_init(2, params, gps, obs, paths, ctypes.byref(h)) == -1
+    assert h.value is None

@@ -1,0 +1,98 @@
+"""Batched form: many independent problems of uneven shape in one persistent
+launch.  Every problem's result must equal its own unbatched run bit for bit
+(the same tile grouping is used), whatever the schedule."""
+import numpy as np
+import pytest
+
+from oracle import mppi
+from paper_2411_03289_amd import gpmppi as B
+from paper_2411_03289_amd import workloads as W
+
+from gpu_util import dev, gpu_step, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    ps = [
+        W.small_problem(K=100, T=12, M=40, n_obs=3, seed_data=71, U_scale=1.0),
+        W.small_problem(K=257, T=7, M=130, n_obs=0, path="eight", seed_data=72, U_scale=0.5),
+        W.small_problem(K=64, T=20, M=64, n_obs=9, seed_data=73),
+        W.small_problem(K=33, T=3, M=1, n_obs=1, path="eight", seed_data=74, U_scale=1.5),
+        W.small_problem(K=500, T=9, M=256, n_obs=5, path="eight", seed_data=75, U_scale=1.0),
+        W.small_problem(K=1, T=15, M=17, n_obs=2, seed_data=76),
+    ]
+    for i, p in enumerate(ps):
+        p.pid = i + 1
+    return ps
+
+
+def _pack(problems):
+    x0 = np.concatenate([p.x0 for p in problems])
+    U = np.concatenate([p.U0.reshape(-1) for p in problems])
+    return x0, U
+
+
+@pytest.mark.parametrize("precision", [B.FP32, B.BF16])
+def test_batch_step_equals_unbatched_runs(precision):
+    t = torch()
+    ps = _problems()
+    b = B.gpmppi_batch_init(ps, precision)
+    U_off, K_off = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    seed = (2003 << 32) + 9
+    Ud, Uo = dev(U), t.empty(U_off[-1], device="cuda")
+    costs = t.full((K_off[-1],), float("nan"), device="cuda")
+    w = t.empty(K_off[-1], device="cuda")
+    B.gpmppi_batch_step(b, dev(x0), Ud, seed, Uo, costs, w)
+    t.cuda.synchronize()
+    Uo, costs, w = Uo.cpu().numpy(), costs.cpu().numpy(), w.cpu().numpy()
+    for i, p in enumerate(ps):
+        U1, S1, w1 = gpu_step(p, precision, seed=seed)
+        np.testing.assert_array_equal(costs[K_off[i]:K_off[i + 1]].astype(np.float64), S1)
+        np.testing.assert_array_equal(Uo[U_off[i]:U_off[i + 1]].reshape(-1, 2).astype(np.float64), U1)
+        np.testing.assert_array_equal(w[K_off[i]:K_off[i + 1]].astype(np.float64), w1)
+
+
+def test_batch_matches_oracle_on_a_problem():
+    t = torch()
+    ps = _problems()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    U_off, K_off = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    seed = 77
+    Uo = t.empty(U_off[-1], device="cuda")
+    costs = t.empty(K_off[-1], device="cuda")
+    B.gpmppi_batch_step(b, dev(x0), dev(U), seed, Uo, costs)
+    t.cuda.synchronize()
+    i = 4
+    S_o, _ = mppi.rollout(ps[i], ps[i].x0, ps[i].U0, seed)
+    S_g = costs.cpu().numpy()[K_off[i]:K_off[i + 1]].astype(np.float64)
+    assert np.all(np.abs(S_g - S_o) <= 1e-5 * np.maximum(S_o, 1.0))
+
+
+def test_batch_closed_loop_graph_equals_eager_and_single_problem_loops():
+    t = torch()
+    ps = _problems()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    U_off, _ = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    n = 4
+    runs = []
+    for use_graph in (False, True):
+        xd, Ud = dev(x0), dev(U)
+        xh = t.empty((n + 1) * len(ps) * 5, device="cuda")
+        B.gpmppi_batch_closed_loop(b, xd, Ud, ps[0].seed, n, 0.3, xh, use_graph=use_graph)
+        t.cuda.synchronize()
+        runs.append((xh.cpu().numpy(), Ud.cpu().numpy(), xd.cpu().numpy()))
+    for a, c in zip(*runs):
+        np.testing.assert_array_equal(a, c)
+    xh = runs[0][0].reshape(n + 1, len(ps), 5)
+    for i, p in enumerate(ps):
+        ctx = B.gpmppi_init(p, B.FP32)
+        xd, Ud = dev(p.x0), dev(p.U0)
+        h = t.empty((n + 1) * 5, device="cuda")
+        B.gpmppi_closed_loop(ctx, xd, Ud, ps[0].seed, n, 0.3, h)
+        t.cuda.synchronize()
+        np.testing.assert_array_equal(h.cpu().numpy().reshape(n + 1, 5), xh[:, i])
+        np.testing.assert_array_equal(Ud.cpu().numpy(), runs[0][1][U_off[i]:U_off[i + 1]])
