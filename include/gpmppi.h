@@ -129,6 +129,19 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2],
 /* Rebuilds both GPs (same M as at init) - once per GP update, off the hot path.  Synchronises. */
 gpmppi_status gpmppi_set_gp(gpmppi_ctx *ctx, const gpmppi_gp gp[2]);
 
+/* Terrain ensemble (Sec. III-A, Eq. 3): n_terr target sets on the context's
+ * GP inputs and hyperparameters (one GP per terrain and output, as a batch GP
+ * with shared inputs).  The rollout then uses mean sum_i w_i m_i and variance
+ * sum_i w_i^2 C_i; with shared inputs and hyperparameters every C_i is the
+ * same, so this is alpha_bar = sum_i w_i alpha_i and a variance factor
+ * sum_i w_i^2.  y [n_terr][2][M] host (row i: terrain i; [o][M] per output),
+ * w [n_terr] host, 1 <= n_terr <= 8.  Synchronises. */
+gpmppi_status gpmppi_set_terrains(gpmppi_ctx *ctx, int32_t n_terr, const double *y, const double *w);
+
+/* New ensemble weights for the terrains already set (e.g. from the weight
+ * estimate of Eq. 4); cheap (no refactorisation).  w [n_terr] host.  Synchronises. */
+gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *ctx, const double *w);
+
 /* One MPPI iteration (Alg. 1, Step 1): rollout of K samples over T steps
  * from x0, then weights w^s = exp(-(S^s - min S)/lambda) / sum and
  * U'_k = sum_s w^s clip(U_k + eps_k^s).

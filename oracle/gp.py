@@ -62,3 +62,26 @@ class ExactGP:
 def build_pair(Z, y, log_ell, log_sf, log_sn):
     """The two residual GPs (linear and angular velocity)."""
     return [ExactGP(Z[o], y[o], log_ell[o], log_sf[o], log_sn[o]) for o in range(2)]
+
+
+def ensemble_predict(terrain_gps, weights, Q):
+    """Eq. (3): the weighted terrain ensemble of the residual GPs.
+
+    terrain_gps[i][o] is the GP of terrain i and output o.  Returns the mean
+    sum_i w_i m_i [n, 2] and the diagonal of sum_i w_i^2 C_i [n, 2], with C_i
+    each terrain's predictive covariance (its diagonal; the outputs are
+    independent GPs)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    mean = np.zeros((Q.shape[0], 2))
+    var = np.zeros((Q.shape[0], 2))
+    for w, gps in zip(weights, terrain_gps):
+        for o in range(2):
+            m, _, s2 = gps[o].predict(Q)
+            mean[:, o] += w * m
+            var[:, o] += w * w * s2
+    return mean, var
+
+
+def build_terrains(Z, terrain_y, log_ell, log_sf, log_sn):
+    """One GP pair per terrain target set terrain_y [n_terr, 2, M]."""
+    return [build_pair(Z, y, log_ell, log_sf, log_sn) for y in terrain_y]

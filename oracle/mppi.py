@@ -37,7 +37,7 @@ READINGS = {
     "R2": "the GP residual is an acceleration: dv = dt m, covariance gains dt^2 s^2",
     "R3": "s^2 = sn^2 + max(0, sf^2 - k^T (K + sn^2 I)^-1 k), the predictive variance",
     "R4": "inducing set = the first M training points (subset of data)",
-    "R5": "one terrain, ensemble weight 1",
+    "R5": "one terrain with weight 1 unless terrain target sets and weights are given (Eq. 3)",
     "R6": "the covariance Jacobian is that of the nominal dynamics only",
     "R7": "Sigma is propagated per sample along its own rollout",
     "R8": "one combined stage cost; slip and goal terms weigh 0",
@@ -76,8 +76,12 @@ def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
     U = np.asarray(U, dtype=np.float64)
     T = U.shape[0]
     dt, tv, tw = p["dt"], p["tau_v"], p["tau_w"]
+    terrains = getattr(problem, "terrain_y", None) is not None
     if gps is None:
-        gps = G.build_pair(problem.Z, problem.y, problem.log_ell, problem.log_sf, problem.log_sn)
+        if terrains:
+            gps = G.build_terrains(problem.Z, problem.terrain_y, problem.log_ell, problem.log_sf, problem.log_sn)
+        else:
+            gps = G.build_pair(problem.Z, problem.y, problem.log_ell, problem.log_sf, problem.log_sn)
     ids = np.arange(K) if sample_ids is None else np.asarray(sample_ids)
     K = len(ids)
     u_all = sampled_controls(U, ids, seed, (p["sig_v"], p["sig_w"]), p["u_min"], p["u_max"],
@@ -95,10 +99,13 @@ def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
     for k in range(T):
         u = u_all[k]
         q = np.concatenate([x[:, 3:5], u], axis=1)
-        m = np.empty((K, 2))
-        s2 = np.empty((K, 2))
-        for o in range(2):
-            m[:, o], _, s2[:, o] = gps[o].predict(q)
+        if terrains:
+            m, s2 = G.ensemble_predict(gps, problem.terrain_w, q)
+        else:
+            m = np.empty((K, 2))
+            s2 = np.empty((K, 2))
+            for o in range(2):
+                m[:, o], _, s2[:, o] = gps[o].predict(q)
         A = D.nominal_jacobian(x, dt, tv, tw)
         x = D.euler_step(x, u, m, dt, tv, tw)
         Sigma = D.covariance_step(Sigma, A, s2, dt)
@@ -158,7 +165,10 @@ def closed_loop(problem, n_steps: int, x0=None, U=None, record=False):
     p = problem.params
     x = np.asarray(problem.x0 if x0 is None else x0, dtype=np.float64).copy()
     U = np.asarray(problem.U0 if U is None else U, dtype=np.float64).copy()
-    gps = G.build_pair(problem.Z, problem.y, problem.log_ell, problem.log_sf, problem.log_sn)
+    if getattr(problem, "terrain_y", None) is not None:
+        gps = G.build_terrains(problem.Z, problem.terrain_y, problem.log_ell, problem.log_sf, problem.log_sn)
+    else:
+        gps = G.build_pair(problem.Z, problem.y, problem.log_ell, problem.log_sf, problem.log_sn)
     xs, Us = [x.copy()], []
     for t in range(n_steps):
         Unew, S, w, _ = iteration(problem, x, U, problem.seed_at(t), gps=gps)

@@ -183,6 +183,31 @@ hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const doubl
     return hipGetLastError();
 }
 
+// alpha = W^T (W y) for another target vector y on the same W (b.u is scratch).
+hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st) {
+    hipLaunchKernelGGL(matvec_lower_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.W, y_d, b.u, Mpad, 0);
+    hipLaunchKernelGGL(matvec_lower_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.W, b.u, alpha_d, Mpad, 1);
+    return hipGetLastError();
+}
+
+__global__ void combine_alpha_kernel(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w,
+                                     double *out64, float *alpha32, float *cza) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= Mpad) return;
+    double a = 0.0;
+    for (int i = 0; i < n_terr; ++i) a += w.w[i] * alpha_terr[(size_t)i * Mpad + j];
+    if (out64) out64[j] = a;
+    alpha32[j] = (float)a;
+    cza[2 * j + 1] = (float)a;
+}
+
+hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w, double *out64,
+                         float *alpha32, float *cza, hipStream_t st) {
+    hipLaunchKernelGGL(combine_alpha_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, alpha_terr, n_terr, Mpad, w,
+                       out64, alpha32, cza);
+    return hipGetLastError();
+}
+
 // Packs the W blocks in the rollout's pair-major order: block index
 // b = 2 (u (u + 1) + it) + side holds rows of tile t = 2u + side and columns of
 // block column it (it <= 2u + 1); entries above the diagonal or beyond M are 0.

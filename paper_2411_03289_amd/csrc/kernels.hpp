@@ -32,6 +32,7 @@ struct GpDev {
     float c2[2];
     float sf2[2];
     float sn2[2];
+    float vscale[2];        // sum_i w_i^2 of a terrain ensemble (1 for a single terrain)
     int Mpad;
     int NT;                 // Mpad / 32
 };
@@ -131,6 +132,14 @@ struct GpBuildBuffers {
 };
 hipError_t build_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double ell[4], double sf2,
                            double sn2, hipStream_t st);
+struct TerrainWeights {
+    double w[8];
+};
+// alpha_bar = sum_i w_i alpha_i (FP64 alpha_terr [n_terr][Mpad] of one output),
+// written to out64 and, in FP32, to alpha32 [Mpad] and the alpha slots of cza.
+hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w, double *out64,
+                         float *alpha32, float *cza, hipStream_t st);
+hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st);
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
                           float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
                           hipStream_t st);

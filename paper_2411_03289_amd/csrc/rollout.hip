@@ -445,7 +445,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     for (int ww = 0; ww < kWaves; ++ww) v2 += vred[ww * S::B + sl];
 #pragma unroll
     for (int p = 0; p < S::parts; ++p) m += pred[p * S::B + sl];
-    var_out = g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2);
+    var_out = g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));
     mean_out = m;
 }
 

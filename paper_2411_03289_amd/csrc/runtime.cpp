@@ -86,6 +86,11 @@ struct gpmppi_ctx {
     float *seg_inv = nullptr;
     uint32_t *flags = nullptr;       // [0] status bits, [1] non-PD flag, [2] closed-loop step counter
     double *A64 = nullptr, *W64 = nullptr, *Z64 = nullptr, *y64 = nullptr, *u64 = nullptr, *al64 = nullptr;
+    // terrain ensemble (Eq. 3): per-terrain alpha on shared inputs and hyperparameters
+    int n_terr = 0;
+    double *alpha_terr = nullptr;    // [2][n_terr][Mpad] FP64 (output-major)
+    std::vector<double> Zh[2], yh[2];
+    double log_ell[2][4] = {}, log_sf[2] = {}, log_sn[2] = {};
     float *U_scratch = nullptr;      // [T][2] new controls inside the closed loop
     float *cost_scratch = nullptr;   // [K]
     // host copies
@@ -177,6 +182,14 @@ gpmppi_status validate_world(const gpmppi_obstacles *ob, const gpmppi_path *pa) 
 
 gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
     const int M = c->M, Mpad = c->Mpad;
+    for (int o = 0; o < 2; ++o) {
+        c->Zh[o].assign(gp[o].Z, gp[o].Z + 4 * M);
+        c->yh[o].assign(gp[o].y, gp[o].y + M);
+        for (int d = 0; d < 4; ++d) c->log_ell[o][d] = gp[o].log_ell[d];
+        c->log_sf[o] = gp[o].log_sf;
+        c->log_sn[o] = gp[o].log_sn;
+    }
+    c->n_terr = 0;
     const double kScale = std::sqrt(0.5 / std::log(2.0));   // sqrt(log2(e) / 2)
     for (int o = 0; o < 2; ++o) {
         std::vector<double> y(Mpad, 0.0);
@@ -205,6 +218,7 @@ gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
         c->gp.c2[o] = (float)(2.0 * gp[o].log_sf / std::log(2.0));
         c->gp.sf2[o] = (float)sf2;
         c->gp.sn2[o] = (float)sn2;
+        c->gp.vscale[o] = 1.0f;
     }
     return GPMPPI_OK;
 }
@@ -394,6 +408,73 @@ gpmppi_status gpmppi_set_gp(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
     if ((st = validate_gp(gp)) != GPMPPI_OK) return st;
     if (gp[0].M != c->M) return fail(GPMPPI_E_INVALID, "M must stay %d (got %d)", c->M, gp[0].M);
     return build_gps(c, gp);
+}
+
+gpmppi_status gpmppi_set_terrains(gpmppi_ctx *c, int32_t n_terr, const double *y, const double *w) {
+    g_last_error.clear();
+    if (!c || !y || !w) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n_terr < 1 || n_terr > 8) return fail(GPMPPI_E_INVALID, "terrain count must lie in [1, 8]");
+    const int M = c->M, Mpad = c->Mpad;
+    for (long long i = 0; i < (long long)n_terr * 2 * M; ++i)
+        if (!is_fin(y[i])) return fail(GPMPPI_E_NONFINITE, "non-finite terrain target");
+    for (int i = 0; i < n_terr; ++i)
+        if (!is_fin(w[i])) return fail(GPMPPI_E_NONFINITE, "non-finite terrain weight");
+    if (c->alpha_terr) {
+        (void)hipFree(c->alpha_terr);
+        c->owned.erase(std::remove(c->owned.begin(), c->owned.end(), (void *)c->alpha_terr), c->owned.end());
+        c->alpha_terr = nullptr;
+    }
+    gpmppi_status st = GPMPPI_OK;
+    // layout [o][i][Mpad] so that one output's terrains are contiguous
+    c->alpha_terr = dev_alloc<double>((size_t)2 * n_terr * Mpad, st);
+    if (st != GPMPPI_OK) return st;
+    c->owned.push_back(c->alpha_terr);
+    std::vector<double> yp(Mpad, 0.0);
+    for (int o = 0; o < 2; ++o) {
+        // factor this output once (the targets do not enter L or W), then one alpha per terrain
+        double ell[4];
+        for (int d = 0; d < 4; ++d) ell[d] = std::exp(c->log_ell[o][d]);
+        HIP_TRY(hipMemcpy(c->Z64, c->Zh[o].data(), sizeof(double) * 4 * M, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(c->y64, 0, sizeof(double) * Mpad));
+        HIP_TRY(hipMemset(c->flags + 1, 0, sizeof(uint32_t)));
+        GpBuildBuffers b{c->A64, c->W64, c->Z64, c->y64, c->u64, c->al64, c->flags + 1};
+        HIP_TRY(build_gp_output(b, M, Mpad, ell, std::exp(2.0 * c->log_sf[o]), std::exp(2.0 * c->log_sn[o]),
+                                nullptr));
+        uint32_t notpd = 0;
+        HIP_TRY(hipMemcpy(&notpd, c->flags + 1, sizeof notpd, hipMemcpyDeviceToHost));
+        if (notpd) return fail(GPMPPI_E_NOT_PD, "GP %d: K(Z,Z) + sn^2 I is not positive definite", o);
+        for (int i = 0; i < n_terr; ++i) {
+            std::fill(yp.begin(), yp.end(), 0.0);
+            std::memcpy(yp.data(), y + ((size_t)i * 2 + o) * M, sizeof(double) * M);
+            HIP_TRY(hipMemcpy(c->y64, yp.data(), sizeof(double) * Mpad, hipMemcpyHostToDevice));
+            HIP_TRY(alpha_for_targets(b, Mpad, c->y64, c->alpha_terr + ((size_t)o * n_terr + i) * Mpad, nullptr));
+            HIP_TRY(hipDeviceSynchronize());
+        }
+    }
+    c->n_terr = n_terr;
+    return gpmppi_set_terrain_weights(c, w);
+}
+
+gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *c, const double *w) {
+    g_last_error.clear();
+    if (!c || !w) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (c->n_terr < 1) return fail(GPMPPI_E_INVALID, "no terrains set (gpmppi_set_terrains)");
+    for (int i = 0; i < c->n_terr; ++i)
+        if (!is_fin(w[i])) return fail(GPMPPI_E_NONFINITE, "non-finite terrain weight");
+    TerrainWeights tw{};
+    double s2 = 0.0;
+    for (int i = 0; i < c->n_terr; ++i) {
+        tw.w[i] = w[i];
+        s2 += w[i] * w[i];
+    }
+    const int Mpad = c->Mpad;
+    for (int o = 0; o < 2; ++o) {
+        HIP_TRY(combine_alpha(c->alpha_terr + (size_t)o * c->n_terr * Mpad, c->n_terr, Mpad, tw, nullptr,
+                              c->alpha + (size_t)o * Mpad, c->cza + (size_t)o * Mpad * 2, nullptr));
+        c->gp.vscale[o] = (float)s2;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    return GPMPPI_OK;
 }
 
 gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, float *costs_d,

@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
         "gpmppi_init": [ctypes.POINTER(gpmppi_params), ctypes.POINTER(gpmppi_gp), ctypes.POINTER(gpmppi_obstacles),
                         ctypes.POINTER(gpmppi_path), ctypes.POINTER(vp)],
         "gpmppi_set_gp": [vp, ctypes.POINTER(gpmppi_gp)],
+        "gpmppi_set_terrains": [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)],
+        "gpmppi_set_terrain_weights": [vp, ctypes.POINTER(f64)],
         "gpmppi_step": [vp, vp, vp, u64, vp, vp, vp, vp],
         "gpmppi_rollout": [vp, vp, vp, u64, vp, ctypes.POINTER(gpmppi_trace), vp],
         "gpmppi_weights_update": [vp, vp, vp, u64, vp, vp, vp],
@@ -211,12 +213,32 @@ def gpmppi_init(problem, precision: int = FP32) -> Context:
     obs, path = _world_structs(problem, keep)
     h = ctypes.c_void_p()
     _check(lib().gpmppi_init(ctypes.byref(params), gps, ctypes.byref(obs), ctypes.byref(path), ctypes.byref(h)))
-    return Context(h.value, dict(K=problem.K, T=problem.T, M=problem.M, precision=precision))
+    ctx = Context(h.value, dict(K=problem.K, T=problem.T, M=problem.M, precision=precision))
+    if getattr(problem, "terrain_y", None) is not None:
+        gpmppi_set_terrains(ctx, problem.terrain_y, problem.terrain_w)
+    return ctx
 
 
 def gpmppi_set_gp(ctx: Context, problem):
     keep: list = []
     _check(lib().gpmppi_set_gp(ctx.handle, _gp_structs(problem, keep)))
+
+
+def gpmppi_set_terrains(ctx: Context, terrain_y, weights):
+    """terrain_y [n_terr, 2, M] targets on the context's GP inputs; weights [n_terr]."""
+    y, yp = _as_c_double(terrain_y)
+    w, wp = _as_c_double(weights)
+    if y.ndim != 3 or y.shape[1:] != (2, ctx.params["M"]) or w.shape != (y.shape[0],):
+        raise GpmppiError(-1, "terrain_y must be [n_terr, 2, M] and weights [n_terr]")
+    _check(lib().gpmppi_set_terrains(ctx.handle, int(y.shape[0]), yp, wp))
+    ctx.params["n_terr"] = int(y.shape[0])
+
+
+def gpmppi_set_terrain_weights(ctx: Context, weights):
+    w, wp = _as_c_double(weights)
+    if w.shape != (ctx.params.get("n_terr", -1),):
+        raise GpmppiError(-1, "weights must have one entry per terrain")
+    _check(lib().gpmppi_set_terrain_weights(ctx.handle, wp))
 
 
 def gpmppi_step(ctx: Context, x0, U, seed: int, U_out, costs, weights=None, stream=None):

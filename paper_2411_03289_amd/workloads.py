@@ -59,6 +59,8 @@ class Problem:
     pid: int = 0           # problem id (Philox counter word 2)
     params: dict = dataclasses.field(default_factory=lambda: dict(DEFAULT_PARAMS))
     name: str = ""
+    terrain_y: Optional[np.ndarray] = None   # [n_terr, 2, M] per-terrain targets on the shared inputs Z
+    terrain_w: Optional[np.ndarray] = None   # [n_terr] ensemble weights
 
     @property
     def M(self) -> int:
@@ -193,3 +195,23 @@ def random_costs(K: int, seed: int, spread: float = 20.0, offset: float = 100.0)
 def random_controls(T: int, seed: int, scale: float = 1.5) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-scale, scale, size=(T, 2))
+
+
+# Per-terrain synthetic residuals on shared inputs (v, w, v_cmd, w_cmd):
+# y = a sin(v w) - c v + N(0, 0.05^2), one (a, c) per terrain.
+TERRAINS = ((0.3, 0.0), (0.15, 0.2), (0.45, -0.1))
+
+
+def add_terrains(problem: Problem, seed: int, weights=(0.5, 0.3, 0.2), n_terr: int = 3) -> Problem:
+    """Gives the problem n_terr target sets on its GP inputs and ensemble weights."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = problem.M
+    ty = np.empty((n_terr, 2, M))
+    for i in range(n_terr):
+        a, c = TERRAINS[i % len(TERRAINS)]
+        for o in range(2):
+            Zo = problem.Z[o]
+            ty[i, o] = a * np.sin(Zo[:, 0] * Zo[:, 1]) - c * Zo[:, 0] + rng.normal(0.0, TARGET_NOISE, size=M)
+    problem.terrain_y = ty
+    problem.terrain_w = np.asarray(weights[:n_terr], dtype=np.float64)
+    return problem

@@ -302,3 +302,27 @@ def test_closed_loop_resynced_steps_and_graph_replay():
         B.gpmppi_plant_shift(ctx, xd, xd, Ud, 0.3)
     t.cuda.synchronize()
     np.testing.assert_array_equal(xd.cpu().numpy(), res[0][0][-5:])
+
+
+# ------------------------------------------------------------------ terrain ensemble (Eq. 3)
+def test_terrain_ensemble_rollout_matches_oracle():
+    pr = W.add_terrains(W.small_problem(K=96, T=12, M=60, n_obs=6, path="eight", seed_data=81, U_scale=1.0),
+                        seed=82, weights=(0.6, 0.25, 0.15))
+    S_g, tr_g = gpu_rollout(pr)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    _check_rollout(pr, S_g, tr_g, S_o, tr_o, "rollout terrains")
+
+
+def test_terrain_weights_select_a_terrain():
+    pr = W.add_terrains(W.small_problem(K=64, T=8, M=48, seed_data=83, U_scale=1.0), seed=84)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        B.gpmppi_set_terrain_weights(ctx, e)
+        single = W.small_problem(K=64, T=8, M=48, seed_data=83, U_scale=1.0)
+        single.y = pr.terrain_y[i].copy()
+        a = gpu_step(pr, ctx=ctx)
+        b = gpu_step(single)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)

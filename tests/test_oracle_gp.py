@@ -90,3 +90,29 @@ def test_not_positive_definite_raises():
     Z = np.zeros((3, 4))   # identical inputs
     with pytest.raises(np.linalg.LinAlgError):
         G.ExactGP(Z, np.zeros(3), np.zeros(4), 0.0, -400.0)   # sn = e^-400 underflows to 0
+
+
+def test_ensemble_reduces_to_single_terrain_and_scales_variance():
+    pr = W.add_terrains(W.small_problem(M=30, seed_data=12), seed=5)
+    tg = G.build_terrains(pr.Z, pr.terrain_y, pr.log_ell, pr.log_sf, pr.log_sn)
+    Q = W.random_queries(80, 13)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        m, v = G.ensemble_predict(tg, e, Q)
+        for o in range(2):
+            mi, _, vi = tg[i][o].predict(Q)
+            np.testing.assert_array_equal(m[:, o], mi)
+            np.testing.assert_array_equal(v[:, o], vi)
+    # shared inputs and hyperparameters: each terrain has the same covariance,
+    # so the ensemble variance is (sum w^2) times it, and the mean is linear in w
+    w = np.array([0.5, 0.3, 0.2])
+    m, v = G.ensemble_predict(tg, w, Q)
+    for o in range(2):
+        _, _, v0 = tg[0][o].predict(Q)
+        np.testing.assert_allclose(v[:, o], np.sum(w**2) * v0, rtol=1e-12)
+        ref = sum(w[i] * tg[i][o].predict(Q)[0] for i in range(3))
+        np.testing.assert_allclose(m[:, o], ref, rtol=1e-12, atol=1e-15)
+        # alpha of the weighted targets = weighted alphas (the GP mean is linear in y)
+        gw = G.ExactGP(pr.Z[o], np.tensordot(w, pr.terrain_y[:, o], 1), pr.log_ell[o], pr.log_sf[o], pr.log_sn[o])
+        np.testing.assert_allclose(gw.predict(Q)[0], m[:, o], rtol=1e-10, atol=1e-13)
