@@ -103,6 +103,14 @@ typedef struct {
     double discount;            /* lane-exit discount base (0.9 in Eq. 11) */
     int32_t precision;          /* gpmppi_precision */
     int32_t problem_id;         /* Philox counter word 2 */
+    /* goal terms of the avoidance cost (Eq. 12): w_goal |p_{k+1} - goal| every step, and w_term once
+       when no step of the rollout comes within goal_tol of the goal (both >= 0; 0 disables) */
+    double w_goal, w_term;
+    double goal[2];
+    double goal_tol;            /* > 0 */
+    int32_t tighten;            /* 0: each sample's constraints use its own propagated Sigma_XY;
+                                   1: Sigma_XY propagated once along the nominal sequence clip(U) with
+                                   the GP mean and variance (Alg. 1 Step 2), shared by all samples */
 } gpmppi_params;
 
 /* Optional per-step outputs of a rollout, all SoA with the sample index
@@ -190,7 +198,8 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *ctx, float *x_d, float *U_d, uint64
  * together: one persistent rollout launch whose workgroups take (problem,
  * sample block) items, longest first, from a device counter, then one update
  * launch with a workgroup per (problem, horizon step).  Results of a problem
- * do not depend on the schedule.  All problems share one precision form. */
+ * do not depend on the schedule.  All problems share one precision form and
+ * use per-sample tightening (tighten = 0). */
 typedef struct gpmppi_batch gpmppi_batch;
 
 /* Creates n problems on the current device, each exactly as gpmppi_init would

@@ -48,6 +48,10 @@ READINGS = {
     "R16": "no control-cost term; baseline rho = min S; U' = sum w clip(U + eps)",
     "R17": "closed-loop plant = nominal Euler + dt 0.3 sin(v w) on v and w",
     "R21": "warm start: shift left and repeat the last control",
+    "R26": "goal terms (Eq. 12): g = w_goal |p_{k+1} - goal| every step; F = w_term once if no step "
+           "of the rollout comes within goal_tol of the goal",
+    "R27": "Step 2 tightening (tighten = 1): Sigma propagated once along the nominal sequence "
+           "(zero noise, GP mean), its Sigma_XY[k] used for every sample's constraints at step k",
 }
 
 
@@ -66,6 +70,16 @@ class Trace:
 
 def param(problem, name):
     return problem.params[name]
+
+
+def nominal_tightening(problem, x0, U, gps=None):
+    """Alg. 1 Step 2: Sigma_XY [T+1, 3] propagated along the nominal controls
+    clip(U) (Eq. 10 with the GP mean and variance, no sampling noise)."""
+    p = dict(problem.params)
+    p.update(sig_v=0.0, sig_w=0.0, tighten=0)
+    nominal = dataclasses.replace(problem, params=p)
+    _, tr = rollout(nominal, x0, U, 0, gps=gps, sample_ids=np.array([0]))
+    return tr.sxy[:, 0, :]
 
 
 def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
@@ -89,6 +103,10 @@ def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
     x = np.tile(np.asarray(x0, dtype=np.float64), (K, 1))
     Sigma = np.zeros((K, 5, 5))
     r = p["half_width"]
+    tight = nominal_tightening(problem, x0, U, gps) if p.get("tighten", 0) == 1 else None
+    w_goal, w_term = p.get("w_goal", 0.0), p.get("w_term", 0.0)
+    goal = np.asarray(p.get("goal", (0.0, 0.0)), dtype=np.float64)
+    d_goal_min = np.full(K, np.inf)
     tr = Trace(x=np.empty((T + 1, K, 5)), sxy=np.empty((T + 1, K, 3)),
                gp_mean=np.empty((T, K, 2)), gp_var=np.empty((T, K, 2)),
                d_lane=np.empty((T, K)), lane_margin=np.empty((T, K)),
@@ -110,11 +128,12 @@ def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
         x = D.euler_step(x, u, m, dt, tv, tw)
         Sigma = D.covariance_step(Sigma, A, s2, dt)
         sxy = np.stack([Sigma[:, 0, 0], Sigma[:, 0, 1], Sigma[:, 1, 1]], axis=1)
+        sxy_c = sxy if tight is None else np.tile(tight[k + 1], (K, 1))
         P = x[:, 0:2]
         d_lane = C.lane_distance(P, problem.path_kind, problem.circle, problem.path_pts)
-        r_bar = C.tightened_lane_radius(r, sxy, p["p_x"])
+        r_bar = C.tightened_lane_radius(r, sxy_c, p["p_x"])
         if problem.obstacles.shape[0]:
-            obs = C.obstacle_margins(P, sxy, problem.obstacles, p["p_x"]).min(axis=1)
+            obs = C.obstacle_margins(P, sxy_c, problem.obstacles, p["p_x"]).min(axis=1)
         else:
             obs = np.full(K, np.inf)
         lane_exit = (d_lane > r_bar).astype(np.float64)
@@ -124,11 +143,16 @@ def rollout(problem, x0, U, seed: int, K: Optional[int] = None, gps=None,
              + p["w_lane"] * p["discount"] ** k * lane_exit
              + p["w_speed"] * (p["v_des"] - x[:, 3]) ** 2
              + p["w_obs"] * collide)
+        d_goal = np.hypot(P[:, 0] - goal[0], P[:, 1] - goal[1])
+        d_goal_min = np.minimum(d_goal_min, d_goal)
+        c = c + w_goal * d_goal
         S += c
         tr.x[k + 1], tr.sxy[k + 1] = x, sxy
         tr.gp_mean[k], tr.gp_var[k] = m, s2
         tr.d_lane[k], tr.lane_margin[k], tr.obs_margin[k] = d_lane, r_bar - d_lane, obs
         tr.stage[k] = c
+    if w_term:
+        S += w_term * (d_goal_min > p.get("goal_tol", 0.5))
     return S, tr
 
 

@@ -51,6 +51,7 @@ struct Geometry {
 
 struct CostWeights {
     float w_var, w_dev, w_lane, w_speed, w_obs, v_des, discount;
+    float w_goal, w_term, goal_x, goal_y, goal_tol;
 };
 
 struct Dyn {
@@ -71,6 +72,7 @@ struct RolloutArgs {
     const float *x0;                // [5]
     const float *U;                 // [T][2]
     float *costs;                   // [K]
+    const float *tight_sxy;         // [T+1][3] Sigma_XY along the nominal sequence, or NULL (per sample)
     gpmppi_trace trace;
 };
 

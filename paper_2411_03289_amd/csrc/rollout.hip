@@ -482,6 +482,7 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
     float p00 = 0, p01 = 0, p02 = 0, p03 = 0, p04 = 0, p11 = 0, p12 = 0, p13 = 0, p14 = 0, p22 = 0,
           p23 = 0, p24 = 0, p33 = 0, p34 = 0, p44 = 0;
     float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
+    float dgoal_min = INFINITY;
 
     if (writer && a.trace.x_d) {
         a.trace.x_d[0 * K + sg] = X;
@@ -556,8 +557,14 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         p44 = a44 * b44 + dt * dt * s2[1];
         X = Xn; Y = Yn; th = thn; v = vn; w_ = wn;
 
-        // ---- chance constraints at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16)
-        const float sa = p00, sb = p01, sc = p11;
+        // ---- chance constraints at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16); with Step 2
+        // tightening the covariance is the nominal sequence's, shared by all samples
+        float sa = p00, sb = p01, sc = p11;
+        if (a.tight_sxy) {
+            sa = a.tight_sxy[3 * (k + 1)];
+            sb = a.tight_sxy[3 * (k + 1) + 1];
+            sc = a.tight_sxy[3 * (k + 1) + 2];
+        }
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
         float best = INFINITY;   // squared distance to the polyline (this part's segments)
@@ -605,6 +612,12 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         float c = cw.w_var * (s2[0] + s2[1]) + cw.w_dev * (dl * geo.inv_half_width) + cw.w_speed * (dv * dv);
         if (dl > rbar) c += cw.w_lane * disc;
         if (om <= 0.0f) c += cw.w_obs;
+        if (cw.w_goal != 0.0f || cw.w_term != 0.0f) {   // goal terms (Eq. 12)
+            const float gx = X - cw.goal_x, gy = Y - cw.goal_y;
+            const float dg = sqrtf(gx * gx + gy * gy);
+            dgoal_min = fminf(dgoal_min, dg);
+            c += cw.w_goal * dg;
+        }
         {
             const float yk = c - Sc;
             const float tk = S_ + yk;
@@ -626,9 +639,9 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
             }
             if (tr.sxy_d) {
                 float *sd = tr.sxy_d + (kk + 1) * 3 * K;
-                sd[0 * K + sg] = sa;
-                sd[1 * K + sg] = sb;
-                sd[2 * K + sg] = sc;
+                sd[0 * K + sg] = p00;
+                sd[1 * K + sg] = p01;
+                sd[2 * K + sg] = p11;
             }
             if (tr.gp_mean_d) {
                 tr.gp_mean_d[(kk * 2 + 0) * K + sg] = m[0];
@@ -646,6 +659,10 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
                 tr.u_d[(kk * 2 + 1) * K + sg] = u.y;
             }
         }
+    }
+    if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
+        const float yk = cw.w_term - Sc;
+        S_ = S_ + yk;
     }
     if (writer) a.costs[sg] = S_;
 }

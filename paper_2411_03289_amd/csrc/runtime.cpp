@@ -93,6 +93,7 @@ struct gpmppi_ctx {
     double log_ell[2][4] = {}, log_sf[2] = {}, log_sn[2] = {};
     float *U_scratch = nullptr;      // [T][2] new controls inside the closed loop
     float *cost_scratch = nullptr;   // [K]
+    float *tight = nullptr;          // [T+1][3] nominal Sigma_XY (Step 2 tightening)
     // host copies
     GpDev gp{};
     Geometry geo{};
@@ -127,6 +128,12 @@ gpmppi_status validate_params(const gpmppi_params *p) {
     if (!(p->p_x > 0 && p->p_x < 1)) return fail(GPMPPI_E_INVALID, "p_x must lie in (0, 1)");
     if (p->precision < 0 || p->precision > 2) return fail(GPMPPI_E_INVALID, "unknown precision %d", p->precision);
     if (p->problem_id < 0) return fail(GPMPPI_E_INVALID, "problem_id must be >= 0");
+    if (!is_fin(p->w_goal) || !is_fin(p->w_term) || !is_fin(p->goal[0]) || !is_fin(p->goal[1]) ||
+        !is_fin(p->goal_tol))
+        return fail(GPMPPI_E_NONFINITE, "non-finite goal parameter");
+    if (p->w_goal < 0 || p->w_term < 0 || !(p->goal_tol > 0))
+        return fail(GPMPPI_E_INVALID, "goal weights must be >= 0 and goal_tol > 0");
+    if (p->tighten != 0 && p->tighten != 1) return fail(GPMPPI_E_INVALID, "tighten must be 0 or 1");
     return GPMPPI_OK;
 }
 
@@ -255,6 +262,21 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     return a;
 }
 
+// Alg. 1 Step 2: one zero-noise sample along clip(U) writes Sigma_XY per step
+// into c->tight; returns the table pointer for the main rollout (or NULL).
+const float *enqueue_tightening(gpmppi_ctx *c, const float *x0, const float *U, const uint32_t *step_counter,
+                                hipStream_t st, hipError_t &err) {
+    err = hipSuccess;
+    if (c->params.tighten != 1) return nullptr;
+    RolloutArgs n = rollout_args(c, x0, U, 0, c->cost_scratch, nullptr, step_counter);
+    n.K = 1;
+    n.noise.sig_v = 0.0f;
+    n.noise.sig_w = 0.0f;
+    n.trace.sxy_d = c->tight;
+    err = launch_rollout(n, c->params.precision, st);
+    return c->tight;
+}
+
 UpdateArgs update_args(const gpmppi_ctx *c, const float *costs, const float *U, uint64_t seed, float *U_out,
                        float *weights, const uint32_t *step_counter) {
     UpdateArgs u{};
@@ -328,6 +350,7 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->al64 = track(dev_alloc<double>((size_t)Mpad, st));
     c->U_scratch = track(dev_alloc<float>((size_t)2 * params->T, st));
     c->cost_scratch = track(dev_alloc<float>((size_t)params->K, st));
+    c->tight = track(dev_alloc<float>((size_t)3 * (params->T + 1) + 1, st));
     if (st != GPMPPI_OK) {
         delete c;
         return st;
@@ -389,7 +412,9 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     g.c_p = (float)c->c_p;
 
     c->cw = CostWeights{(float)params->w_var, (float)params->w_dev, (float)params->w_lane, (float)params->w_speed,
-                        (float)params->w_obs, (float)params->v_des, (float)params->discount};
+                        (float)params->w_obs, (float)params->v_des, (float)params->discount,
+                        (float)params->w_goal, (float)params->w_term, (float)params->goal[0],
+                        (float)params->goal[1], (float)params->goal_tol};
     c->dyn = Dyn{(float)params->dt, (float)(params->dt / params->tau_v), (float)(params->dt / params->tau_w),
                  (float)(1.0 - params->dt / params->tau_v), (float)(1.0 - params->dt / params->tau_w)};
 
@@ -481,7 +506,11 @@ gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d,
                              const gpmppi_trace *trace, void *stream) {
     g_last_error.clear();
     if (!c || !x0_d || !U_d || !costs_d) return fail(GPMPPI_E_INVALID, "NULL argument");
-    const RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
+    hipError_t e;
+    const float *tight = enqueue_tightening(c, x0_d, U_d, nullptr, (hipStream_t)stream, e);
+    HIP_TRY(e);
+    RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
+    a.tight_sxy = tight;
     HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
     return GPMPPI_OK;
 }
@@ -499,7 +528,11 @@ gpmppi_status gpmppi_step(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
                           float *costs_d, float *weights_d, void *stream) {
     g_last_error.clear();
     if (!c || !x0_d || !U_d || !U_out_d || !costs_d) return fail(GPMPPI_E_INVALID, "NULL argument");
-    const RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
+    hipError_t e;
+    const float *tight = enqueue_tightening(c, x0_d, U_d, nullptr, (hipStream_t)stream, e);
+    HIP_TRY(e);
+    RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
+    a.tight_sxy = tight;
     HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
     const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
     HIP_TRY(launch_update(u, (hipStream_t)stream));
@@ -539,7 +572,11 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t
     if (n == 0) return GPMPPI_OK;
     // one control step: rollout -> weights/update -> plant + shift, keyed by seed0 + counter
     auto enqueue = [&](hipStream_t s) -> gpmppi_status {
-        const RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
+        hipError_t e;
+        const float *tight = enqueue_tightening(c, x_d, U_d, counter, s, e);
+        HIP_TRY(e);
+        RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
+        a.tight_sxy = tight;
         HIP_TRY(launch_rollout(a, c->params.precision, s));
         const UpdateArgs u = update_args(c, c->cost_scratch, U_d, seed0, U_d, nullptr, counter);
         HIP_TRY(launch_update(u, s));
@@ -653,6 +690,8 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
         if ((st = validate_params(&params[p])) != GPMPPI_OK) return st;
         if (params[p].precision != params[0].precision)
             return fail(GPMPPI_E_INVALID, "all problems of a batch need the same precision");
+        if (params[p].tighten != 0)
+            return fail(GPMPPI_E_UNSUPPORTED, "batches tighten along each sample's own covariance (tighten = 0)");
         if ((st = validate_gp(&gp[2 * p])) != GPMPPI_OK) return st;
         if ((st = validate_world(&obstacles[p], &paths[p])) != GPMPPI_OK) return st;
     }

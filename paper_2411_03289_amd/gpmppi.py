@@ -53,7 +53,9 @@ class gpmppi_params(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("p_x", ctypes.c_double), ("w_var", ctypes.c_double),
                 ("w_dev", ctypes.c_double), ("w_lane", ctypes.c_double), ("w_speed", ctypes.c_double),
                 ("w_obs", ctypes.c_double), ("v_des", ctypes.c_double), ("discount", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("problem_id", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("problem_id", ctypes.c_int32),
+                ("w_goal", ctypes.c_double), ("w_term", ctypes.c_double), ("goal", ctypes.c_double * 2),
+                ("goal_tol", ctypes.c_double), ("tighten", ctypes.c_int32)]
 
 
 class gpmppi_trace(ctypes.Structure):
@@ -173,7 +175,9 @@ def make_params(problem, precision: int = FP32) -> gpmppi_params:
         sig_w=p["sig_w"], u_min=(ctypes.c_double * 2)(*p["u_min"]), u_max=(ctypes.c_double * 2)(*p["u_max"]),
         lambda_=p["lam"], p_x=p["p_x"], w_var=p["w_var"], w_dev=p["w_dev"], w_lane=p["w_lane"],
         w_speed=p["w_speed"], w_obs=p["w_obs"], v_des=p["v_des"], discount=p["discount"],
-        precision=precision, problem_id=problem.pid)
+        precision=precision, problem_id=problem.pid, w_goal=p.get("w_goal", 0.0), w_term=p.get("w_term", 0.0),
+        goal=(ctypes.c_double * 2)(*p.get("goal", (0.0, 0.0))), goal_tol=p.get("goal_tol", 0.5),
+        tighten=int(p.get("tighten", 0)))
 
 
 def _gp_structs(problem, keep: list):

@@ -33,7 +33,20 @@ DEFAULT_PARAMS = dict(
     lam=1.0, p_x=0.95,                      # MPPI temperature, chance level
     w_var=1.0, w_dev=0.5, w_lane=1.0, w_speed=0.1, w_obs=1.0,
     v_des=2.0, discount=0.9, half_width=1.0,
+    w_goal=0.0, w_term=0.0, goal=(0.0, 0.0), goal_tol=0.5,   # goal terms of Eq. (12), off by default
+    tighten=0,                                               # 1: tighten along the nominal sequence
 )
+
+
+def task_params(task: str, goal=(8.0, 0.0)) -> dict:
+    """Weight presets switching between the paper's two tasks (Sec. III-B):
+    path tracking (Eq. 11 terms) or obstacle avoidance towards a goal (Eq. 12)."""
+    if task == "track":
+        return dict(w_var=1.0, w_dev=0.5, w_lane=1.0, w_speed=0.1, w_obs=0.0, w_goal=0.0, w_term=0.0)
+    if task == "avoid":
+        return dict(w_var=1.0, w_dev=0.0, w_lane=0.0, w_speed=0.0, w_obs=1.0, w_goal=0.2, w_term=1.0,
+                    goal=tuple(goal), goal_tol=0.5)
+    raise ValueError(task)
 
 RESIDUAL_AMPLITUDE = 0.3   # synthetic residual 0.3 sin(v w) (also the plant's)
 TARGET_NOISE = 0.05

@@ -326,3 +326,18 @@ def test_terrain_weights_select_a_terrain():
         b = gpu_step(single)
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ goal terms (Eq. 12) and Step 2 tightening
+@pytest.mark.parametrize("mode", ["goal_reached", "goal_missed", "step2"])
+def test_goal_terms_and_step2_tightening(mode):
+    pr = W.small_problem(K=80, T=14, M=50, n_obs=7, path="eight", seed_data=91, U_scale=1.0)
+    if mode == "step2":
+        pr.params["tighten"] = 1
+    else:
+        pr.params.update(W.task_params("avoid", goal=(0.3, 0.2) if mode == "goal_reached" else (6.0, -6.0)))
+    S_g, tr_g = gpu_rollout(pr)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"rollout {mode}")
+    U_g, S2, _ = gpu_step(pr)
+    np.testing.assert_array_equal(S2, S_g)

@@ -158,3 +158,43 @@ def test_flip_budget_counts_near_threshold_indicators():
     assert np.all(mppi.flip_budget(pr, tr, 1e-9) == 0.0)
     wide = mppi.flip_budget(pr, tr, 10.0)
     assert wide[0] == pytest.approx(np.sum(0.9 ** np.arange(40)) + 40.0, rel=1e-12)
+
+
+def test_goal_terms_closed_form():
+    T = 30
+    pr = _straight_line_problem(T)
+    pr.obstacles = np.zeros((0, 3))
+    pr.params.update(w_goal=0.2, w_term=1.5, goal=(5.0, 2.0), goal_tol=0.3)
+    p0 = _straight_line_problem(T)
+    p0.obstacles = np.zeros((0, 3))
+    base = mppi.rollout(p0, p0.x0, p0.U0, p0.seed)[0]
+    S, tr = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    Y = 2.0 * pr.params["dt"] * (np.arange(T) + 1)
+    dg = np.abs(Y - 2.0)
+    assert dg.min() < 0.3   # the straight line passes the goal: no terminal cost
+    np.testing.assert_allclose(S - base, 0.2 * dg.sum(), rtol=1e-12)
+    pr.params["goal"] = (8.0, 2.0)   # 3 m off the line: never reached
+    S2, _ = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    dg2 = np.hypot(3.0, Y - 2.0)
+    np.testing.assert_allclose(S2 - base, 0.2 * dg2.sum() + 1.5, rtol=1e-12)
+
+
+def test_step2_tightening_uses_the_nominal_covariance():
+    pr = W.small_problem(K=40, T=10, M=20, n_obs=6, path="eight", seed_data=17, U_scale=1.0)
+    pr.params["tighten"] = 1
+    S, tr = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    nom = mppi.nominal_tightening(pr, pr.x0, pr.U0)
+    # the nominal covariance equals a zero-noise single-sample rollout's
+    q = W.small_problem(K=40, T=10, M=20, n_obs=6, path="eight", seed_data=17, U_scale=1.0)
+    q.params.update(sig_v=0.0, sig_w=0.0)
+    _, trq = mppi.rollout(q, q.x0, q.U0, 0, sample_ids=np.array([3]))
+    np.testing.assert_array_equal(nom, trq.sxy[:, 0])
+    from oracle import constraints as C
+    rbar = C.tightened_lane_radius(pr.params["half_width"], nom[1:], pr.params["p_x"])
+    np.testing.assert_allclose(tr.lane_margin, rbar[:, None] - tr.d_lane, rtol=1e-13, atol=1e-13)
+    # with no noise every sample is the nominal: both modes agree
+    q.params["tighten"] = 1
+    Sa, _ = mppi.rollout(q, q.x0, q.U0, 0)
+    q.params["tighten"] = 0
+    Sb, _ = mppi.rollout(q, q.x0, q.U0, 0)
+    np.testing.assert_allclose(Sa, Sb, rtol=1e-13)
