@@ -150,6 +150,16 @@ gpmppi_status gpmppi_set_terrains(gpmppi_ctx *ctx, int32_t n_terr, const double 
  * estimate of Eq. 4); cheap (no refactorisation).  w [n_terr] host.  Synchronises. */
 gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *ctx, const double *w);
 
+/* Terrain-weight estimate (Eq. 4, Alg. 1 Step 3), host-only (needs no device):
+ * minimises ||Yv - Fv w||^2 + ||Yw - Fw w||^2 + gamma ||w - w_prev||_1 subject to
+ * 0 <= w_i <= 1 and sum_i w_i = 1.  Yv, Yw [H] measured residuals of the last H
+ * steps; Fv, Fw [H][n] row-major, terrain i's GP mean at step h; w_prev, w_out
+ * [n] host arrays; 1 <= n <= 8, H >= 1, gamma >= 0.  Exact pairwise descent:
+ * every move minimises the convex piecewise-quadratic objective along
+ * e_i - e_j in closed form; it stops when no move exceeds 1e-15. */
+gpmppi_status gpmppi_terrain_weights(int32_t H, int32_t n, const double *Yv, const double *Yw, const double *Fv,
+                                     const double *Fw, const double *w_prev, double gamma, double *w_out);
+
 /* One MPPI iteration (Alg. 1, Step 1): rollout of K samples over T steps
  * from x0, then weights w^s = exp(-(S^s - min S)/lambda) / sum and
  * U'_k = sum_s w^s clip(U_k + eps_k^s).

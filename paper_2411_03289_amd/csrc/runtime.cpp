@@ -70,6 +70,10 @@ T *dev_alloc(size_t n, gpmppi_status &st) {
 
 }  // namespace
 
+namespace gpmppi {
+gpmppi_status set_error(gpmppi_status st, const char *msg) { return fail(st, "%s", msg); }
+}  // namespace gpmppi
+
 struct gpmppi_ctx {
     int device = 0;
     gpmppi_params params{};

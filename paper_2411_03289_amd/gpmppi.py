@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_set_gp": [vp, ctypes.POINTER(gpmppi_gp)],
         "gpmppi_set_terrains": [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)],
         "gpmppi_set_terrain_weights": [vp, ctypes.POINTER(f64)],
+        "gpmppi_terrain_weights": [i32, i32] + [ctypes.POINTER(f64)] * 5 + [f64, ctypes.POINTER(f64)],
         "gpmppi_step": [vp, vp, vp, u64, vp, vp, vp, vp],
         "gpmppi_rollout": [vp, vp, vp, u64, vp, ctypes.POINTER(gpmppi_trace), vp],
         "gpmppi_weights_update": [vp, vp, vp, u64, vp, vp, vp],
@@ -243,6 +244,21 @@ def gpmppi_set_terrain_weights(ctx: Context, weights):
     if w.shape != (ctx.params.get("n_terr", -1),):
         raise GpmppiError(-1, "weights must have one entry per terrain")
     _check(lib().gpmppi_set_terrain_weights(ctx.handle, wp))
+
+
+def gpmppi_terrain_weights(Yv, Yw, Fv, Fw, w_prev, gamma: float) -> np.ndarray:
+    """Eq. (4) on the host: returns the new terrain weights [n]."""
+    Yv, Yvp = _as_c_double(Yv)
+    Yw, Ywp = _as_c_double(Yw)
+    Fv, Fvp = _as_c_double(Fv)
+    Fw, Fwp = _as_c_double(Fw)
+    wp, wpp = _as_c_double(w_prev)
+    H, n = Fv.shape
+    if Yv.shape != (H,) or Yw.shape != (H,) or Fw.shape != (H, n) or wp.shape != (n,):
+        raise GpmppiError(-1, "shapes: Yv, Yw [H]; Fv, Fw [H, n]; w_prev [n]")
+    out = np.empty(n)
+    _check(lib().gpmppi_terrain_weights(H, n, Yvp, Ywp, Fvp, Fwp, wpp, float(gamma), out.ctypes.data_as(_dp)))
+    return out
 
 
 def gpmppi_step(ctx: Context, x0, U, seed: int, U_out, costs, weights=None, stream=None):
