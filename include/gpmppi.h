@@ -150,6 +150,11 @@ gpmppi_status gpmppi_set_terrains(gpmppi_ctx *ctx, int32_t n_terr, const double 
  * estimate of Eq. 4); cheap (no refactorisation).  w [n_terr] host.  Synchronises. */
 gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *ctx, const double *w);
 
+/* Each terrain's GP means at n queries q = (v, w, v_cmd, w_cmd): the rows
+ * F[h][i] of Eq. (4).  q_d [n][4] device; out_d [n][n_terr][2] device
+ * (output o = 0 linear, 1 angular).  Needs terrains (gpmppi_set_terrains). */
+gpmppi_status gpmppi_terrain_means(gpmppi_ctx *ctx, const float *q_d, int32_t n, float *out_d, void *stream);
+
 /* Terrain-weight estimate (Eq. 4, Alg. 1 Step 3), host-only (needs no device):
  * minimises ||Yv - Fv w||^2 + ||Yw - Fw w||^2 + gamma ||w - w_prev||_1 subject to
  * 0 <= w_i <= 1 and sum_i w_i = 1.  Yv, Yw [H] measured residuals of the last H

@@ -208,6 +208,49 @@ hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, Terrain
     return hipGetLastError();
 }
 
+// Terrain means at n queries: out[q][i][o] = k_o(q)^T alpha_{o,i}; one
+// workgroup per query, threads over training points, FP64 accumulation of the
+// FP32 kernel values.  alpha_terr is [2][n_terr][Mpad] FP64.
+__global__ __launch_bounds__(256) void terrain_means_kernel(const float *q, int n, const float *zs, const double *alpha_terr,
+                                                            int n_terr, int Mpad, float s00, float s01, float s02,
+                                                            float s03, float s10, float s11, float s12, float s13,
+                                                            float c20, float c21, float *out) {
+    __shared__ double red[8][4];
+    const int qi = blockIdx.x, tid = threadIdx.x;
+    const float4 qq = reinterpret_cast<const float4 *>(q)[qi];
+    for (int o = 0; o < 2; ++o) {
+        const float sc[4] = {o ? s10 : s00, o ? s11 : s01, o ? s12 : s02, o ? s13 : s03};
+        const float qs[4] = {qq.x * sc[0], qq.y * sc[1], qq.z * sc[2], qq.w * sc[3]};
+        const float c2 = o ? c21 : c20;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = tid; j < Mpad; j += 256) {
+            const float4 z = reinterpret_cast<const float4 *>(zs)[(size_t)o * Mpad + j];
+            const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
+            const double kv = (double)exp2f(c2 - (d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3));
+            for (int i = 0; i < n_terr; ++i) acc[i] += kv * alpha_terr[((size_t)o * n_terr + i) * Mpad + j];
+        }
+        for (int i = 0; i < n_terr; ++i) {
+            double v = acc[i];
+            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+            if ((tid & 63) == 0) red[i][tid >> 6] = v;
+        }
+        __syncthreads();
+        if (tid < n_terr) {
+            const double v = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+            out[((size_t)qi * n_terr + tid) * 2 + o] = (float)v;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_terrain_means(const float *q, int n, const GpDev &g, const double *alpha_terr, int n_terr,
+                                float *out, hipStream_t st) {
+    hipLaunchKernelGGL(terrain_means_kernel, dim3(n), dim3(256), 0, st, q, n, g.zs, alpha_terr, n_terr, g.Mpad,
+                       g.scale[0][0], g.scale[0][1], g.scale[0][2], g.scale[0][3], g.scale[1][0], g.scale[1][1],
+                       g.scale[1][2], g.scale[1][3], g.c2[0], g.c2[1], out);
+    return hipGetLastError();
+}
+
 // Packs the W blocks in the rollout's pair-major order: block index
 // b = 2 (u (u + 1) + it) + side holds rows of tile t = 2u + side and columns of
 // block column it (it <= 2u + 1); entries above the diagonal or beyond M are 0.

@@ -141,6 +141,8 @@ struct TerrainWeights {
 // written to out64 and, in FP32, to alpha32 [Mpad] and the alpha slots of cza.
 hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w, double *out64,
                          float *alpha32, float *cza, hipStream_t st);
+hipError_t launch_terrain_means(const float *q, int n, const GpDev &g, const double *alpha_terr, int n_terr,
+                                float *out, hipStream_t st);
 hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st);
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
                           float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,

@@ -506,6 +506,15 @@ gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *c, const double *w) {
     return GPMPPI_OK;
 }
 
+gpmppi_status gpmppi_terrain_means(gpmppi_ctx *c, const float *q_d, int32_t n, float *out_d, void *stream) {
+    g_last_error.clear();
+    if (!c || !q_d || !out_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (n < 1) return fail(GPMPPI_E_INVALID, "n must be >= 1");
+    if (c->n_terr < 1) return fail(GPMPPI_E_INVALID, "no terrains set (gpmppi_set_terrains)");
+    HIP_TRY(launch_terrain_means(q_d, n, c->gp, c->alpha_terr, c->n_terr, out_d, (hipStream_t)stream));
+    return GPMPPI_OK;
+}
+
 gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, float *costs_d,
                              const gpmppi_trace *trace, void *stream) {
     g_last_error.clear();

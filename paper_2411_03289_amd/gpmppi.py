@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_set_terrains": [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)],
         "gpmppi_set_terrain_weights": [vp, ctypes.POINTER(f64)],
         "gpmppi_terrain_weights": [i32, i32] + [ctypes.POINTER(f64)] * 5 + [f64, ctypes.POINTER(f64)],
+        "gpmppi_terrain_means": [vp, vp, i32, vp, vp],
         "gpmppi_step": [vp, vp, vp, u64, vp, vp, vp, vp],
         "gpmppi_rollout": [vp, vp, vp, u64, vp, ctypes.POINTER(gpmppi_trace), vp],
         "gpmppi_weights_update": [vp, vp, vp, u64, vp, vp, vp],
@@ -244,6 +245,12 @@ def gpmppi_set_terrain_weights(ctx: Context, weights):
     if w.shape != (ctx.params.get("n_terr", -1),):
         raise GpmppiError(-1, "weights must have one entry per terrain")
     _check(lib().gpmppi_set_terrain_weights(ctx.handle, wp))
+
+
+def gpmppi_terrain_means(ctx: Context, q, out, stream=None):
+    n, nt = int(q.shape[0]), ctx.params.get("n_terr", 0)
+    _check(lib().gpmppi_terrain_means(ctx.handle, _dev(q, 4 * n, "q"), n, _dev(out, n * max(nt, 1) * 2, "out"),
+                                      _stream(stream)))
 
 
 def gpmppi_terrain_weights(Yv, Yw, Fv, Fw, w_prev, gamma: float) -> np.ndarray:

@@ -341,3 +341,27 @@ def test_goal_terms_and_step2_tightening(mode):
     _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"rollout {mode}")
     U_g, S2, _ = gpu_step(pr)
     np.testing.assert_array_equal(S2, S_g)
+
+
+def test_terrain_means_feed_the_weight_estimate():
+    t = torch()
+    pr = W.add_terrains(W.small_problem(K=64, T=8, M=70, seed_data=85), seed=86)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    q = W.random_queries(40, 87)
+    out = t.empty(40 * 3 * 2, device="cuda")
+    B.gpmppi_terrain_means(ctx, dev(q), out)
+    t.cuda.synchronize()
+    F = out.cpu().numpy().reshape(40, 3, 2).astype(np.float64)
+    tg = G.build_terrains(pr.Z, pr.terrain_y, pr.log_ell, pr.log_sf, pr.log_sn)
+    for i in range(3):
+        for o in range(2):
+            m, _, _ = tg[i][o].predict(q)
+            absdot = np.abs(G.se_ard(q, tg[i][o].Z, tg[i][o].log_ell, tg[i][o].log_sf)) @ np.abs(tg[i][o].alpha)
+            assert np.all(np.abs(F[:, i, o] - m) <= 1e-5 + 8 * EPS32 * absdot)
+    # measurements generated by terrain 2: the estimate (Eq. 4) recovers it
+    from oracle import terrain as TR
+    Yv, Yw = F[:, 2, 0].copy(), F[:, 2, 1].copy()
+    w = B.gpmppi_terrain_weights(Yv, Yw, F[:, :, 0], F[:, :, 1], np.full(3, 1 / 3), 0.0)
+    np.testing.assert_allclose(w, [0, 0, 1], atol=1e-6)
+    np.testing.assert_allclose(w, TR.solve_weights(Yv, Yw, F[:, :, 0], F[:, :, 1], np.full(3, 1 / 3), 0.0),
+                               atol=1e-6)
