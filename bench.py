@@ -8,6 +8,10 @@ config 2).  One step = the whole hot path: rollout (noise, GP mean/variance,
 dynamics, covariance, chance constraints, costs) + weights + control update,
 with every input resident in device memory.
 
+Before timing, the library's autotuner picks each form's launch shape
+(sample groups per workgroup, start of the walk over W); the choice is
+reported per form.
+
 Forms: fp32 (FP32 matrix cores), bf16x3 (hi+lo BF16 splits), bf16 (plain
 BF16) for the variance contraction k^T (K + sn^2 I)^-1 k.  Each form is timed
 for --warmup + --steps iterations; the reported `value` is that of the fastest
@@ -66,6 +70,7 @@ def main():
     ap.add_argument("--copy-calibrate-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path is single-GPU (multi-GPU sharding is design only); "
@@ -105,7 +110,8 @@ def main():
         costs = torch.empty(K, **f32)
         weights = torch.empty(K, **f32)
         stream = torch.cuda.current_stream()
-        log(f"[bench] form={name} warmup={args.warmup}")
+        shape = B.gpmppi_get_tuning(ctx) if args.no_tune else B.gpmppi_tune(ctx, x0, U, pr.seed, 2, stream)
+        log(f"[bench] form={name} shape={shape} warmup={args.warmup}")
         for _ in range(args.warmup):
             B.gpmppi_rollout(ctx, x0, U, pr.seed, costs, None, stream)
             B.gpmppi_weights_update(ctx, costs, U, pr.seed, U_out, weights, stream)
@@ -129,7 +135,8 @@ def main():
         u_err = float(np.max(np.abs(U_out.cpu().numpy().astype(np.float64) - U_ref))) if U_ref is not None else None
         results[name] = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall / args.steps,
                              sample_steps_per_s=K * T / (ms * 1e-3), rollout_kernel_ms=rollout_ms,
-                             u_err_vs_fp64=u_err)
+                             u_err_vs_fp64=u_err,
+                             shape={k: shape[k] for k in ("groups", "rotate")})
         log(f"[bench] form={name} {ms:.3f} ms/step rollout {rollout_ms:.3f} ms U err {u_err}")
         del ctx
 

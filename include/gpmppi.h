@@ -208,6 +208,31 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *ctx, float *x_d, float *U_d, uint64
                                  double amplitude, float *x_hist_d, float *U0_hist_d,
                                  int32_t use_graph, void *stream);
 
+/* ------------------------------------------------------------------ launch shapes
+ * The rollout's launch shape, chosen per context (or batch) by measurement.
+ * None of these changes what is computed; they change the grouping of the
+ * variance contraction's partial sums, so results differ between shapes only
+ * by FP32 rounding.  Defaults: the largest group count that fits LDS,
+ * rotate = 1, one workgroup per compute unit per 80 KB of LDS (at most 2),
+ * longest items first. */
+typedef struct {
+    int32_t groups;      /* sample groups of 32 lanes per workgroup: 1 or 2 (2 only where the k operand fits LDS) */
+    int32_t rotate;      /* 1: each workgroup starts its walk over W at a block-dependent row-pair; 0: at pair 0 */
+    int32_t wg_per_cu;   /* batches: persistent workgroups per compute unit, 1 or 2 (LDS permitting) */
+    int32_t order;       /* batches: 0 = items longest first, 1 = problem order */
+    double ms;           /* tune: mean rollout time of this shape in ms; ignored by set */
+} gpmppi_tuning;
+
+/* Autotuner: times every admissible shape with HIP events on `stream`
+ * (1 warm-up + reps rollouts each, reps in [1, 100], into internal scratch
+ * costs; x0_d [5] and U_d [T][2] as for gpmppi_rollout), installs the fastest
+ * and writes it, with its time, to *chosen (may be NULL).  Synchronises. */
+gpmppi_status gpmppi_tune(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
+                          gpmppi_tuning *chosen, void *stream);
+/* Installs a shape (wg_per_cu and order are ignored for a context). */
+gpmppi_status gpmppi_set_tuning(gpmppi_ctx *ctx, const gpmppi_tuning *t);
+gpmppi_status gpmppi_get_tuning(const gpmppi_ctx *ctx, gpmppi_tuning *t);
+
 /* ------------------------------------------------------------------ batches
  * Many independent problems (uneven K, T, M, obstacle count and track) run
  * together: one persistent rollout launch whose workgroups take (problem,
@@ -242,6 +267,13 @@ gpmppi_status gpmppi_batch_step(gpmppi_batch *b, const float *x0_d, const float 
  * use_graph != 0 captures one step in a HIP graph and replays it. */
 gpmppi_status gpmppi_batch_closed_loop(gpmppi_batch *b, float *x_d, float *U_d, uint64_t seed0, int32_t n_steps,
                                        double amplitude, float *x_hist_d, int32_t use_graph, void *stream);
+
+/* Batch autotuner: as gpmppi_tune over the batch's persistent rollout
+ * (groups x rotate x wg_per_cu x order), with x0_d [n][5] and packed U_d. */
+gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
+                                gpmppi_tuning *chosen, void *stream);
+gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t);
+gpmppi_status gpmppi_batch_get_tuning(const gpmppi_batch *b, gpmppi_tuning *t);
 
 /* Frees the batch (NULL is accepted). */
 void gpmppi_batch_destroy(gpmppi_batch *b);

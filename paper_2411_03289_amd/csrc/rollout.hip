@@ -751,8 +751,7 @@ static int groups_for(int precision, int Mpad) {
     return need2 <= budget ? 2 : 1;
 }
 
-size_t rollout_lds_bytes(int precision, int Mpad) {
-    const int G = groups_for(precision, Mpad);
+size_t rollout_lds_bytes(int precision, int G, int Mpad) {
     switch (precision) {
         case GPMPPI_FP32: return G == 2 ? dyn_lds_bytes<GPMPPI_FP32, 2>(Mpad) : dyn_lds_bytes<GPMPPI_FP32, 1>(Mpad);
         case GPMPPI_BF16: return G == 2 ? dyn_lds_bytes<GPMPPI_BF16, 2>(Mpad) : dyn_lds_bytes<GPMPPI_BF16, 1>(Mpad);
@@ -791,6 +790,7 @@ int rollout_groups(int precision, int Mpad) { return groups_for(precision, Mpad)
 
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
                                 int precision, int G, int Mpad_max, int grid, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, Mpad_max) || grid < 1) return hipErrorInvalidValue;
     switch (precision) {
         case GPMPPI_FP32:
             return G == 2 ? launch_rollout_batch_t<GPMPPI_FP32, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
@@ -804,8 +804,8 @@ hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d,
     }
 }
 
-hipError_t launch_rollout(const RolloutArgs &a, int precision, hipStream_t st) {
-    const int G = groups_for(precision, a.gp.Mpad);
+hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, a.gp.Mpad)) return hipErrorInvalidValue;
     switch (precision) {
         case GPMPPI_FP32: return G == 2 ? launch_rollout_t<GPMPPI_FP32, 2>(a, st) : launch_rollout_t<GPMPPI_FP32, 1>(a, st);
         case GPMPPI_BF16: return G == 2 ? launch_rollout_t<GPMPPI_BF16, 2>(a, st) : launch_rollout_t<GPMPPI_BF16, 1>(a, st);

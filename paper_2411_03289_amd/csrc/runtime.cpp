@@ -81,7 +81,8 @@ struct gpmppi_ctx {
     double z_p = 0, c_p = 0;
     // device buffers
     float *zs = nullptr, *alpha = nullptr, *zs2 = nullptr, *cza = nullptr;
-    int rotate = 1;
+    int groups = 1;                  // sample groups of 32 per rollout workgroup (tuned)
+    int rotate = 1;                  // block-dependent start of the walk over W (tuned)
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
     long long w32_stride = 0, wb_stride = 0;
@@ -277,7 +278,7 @@ const float *enqueue_tightening(gpmppi_ctx *c, const float *x0, const float *U, 
     n.noise.sig_v = 0.0f;
     n.noise.sig_w = 0.0f;
     n.trace.sxy_d = c->tight;
-    err = launch_rollout(n, c->params.precision, st);
+    err = launch_rollout(n, c->params.precision, c->groups, st);
     return c->tight;
 }
 
@@ -391,13 +392,13 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->gp.alpha = c->alpha;
     c->gp.zs2 = c->zs2;
     c->gp.cza = c->cza;
-    if (const char *r = std::getenv("GPMPPI_ROTATE")) c->rotate = std::atoi(r);
     c->gp.w32 = c->w32;
     c->gp.wbh = c->wbh;
     c->gp.wbl = c->wbl;
     c->gp.w32_stride = c->w32_stride;
     c->gp.wb_stride = c->wb_stride;
     c->gp.Mpad = Mpad;
+    c->groups = rollout_groups(params->precision, Mpad);
     c->gp.NT = NT;
 
     Geometry &g = c->geo;
@@ -524,7 +525,7 @@ gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d,
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, (hipStream_t)stream));
     return GPMPPI_OK;
 }
 
@@ -546,7 +547,7 @@ gpmppi_status gpmppi_step(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, (hipStream_t)stream));
     const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
     HIP_TRY(launch_update(u, (hipStream_t)stream));
     return GPMPPI_OK;
@@ -590,7 +591,7 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t
         HIP_TRY(e);
         RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
         a.tight_sxy = tight;
-        HIP_TRY(launch_rollout(a, c->params.precision, s));
+        HIP_TRY(launch_rollout(a, c->params.precision, c->groups, s));
         const UpdateArgs u = update_args(c, c->cost_scratch, U_d, seed0, U_d, nullptr, counter);
         HIP_TRY(launch_update(u, s));
         HIP_TRY(launch_plant_shift(x_d, x_d, U_d, c->params.T, c->dyn, (float)amplitude, counter, x_hist_d,
@@ -659,19 +660,23 @@ gpmppi_status gpmppi_info(const gpmppi_ctx *c, int32_t *M_pad, double *z_p, doub
 }  // extern "C"
 
 struct gpmppi_batch {
-    int n = 0, precision = 0, G = 2, Mpad_max = 0, grid = 0;
+    int n = 0, precision = 0, Mpad_max = 0, grid = 0, cus = 1;
+    int G = 1, G_max = 1, rotate = 1, wg_per_cu = 1, wg_per_cu_max = 1, order = 0;
     std::vector<gpmppi_ctx *> ctx;
     std::vector<long long> U_off, K_off;   // n + 1 each
+    std::vector<double> cost;              // estimated rollout cost of one sample block, per problem
+    std::vector<RolloutArgs> ra_h;         // host copy of the per-problem rollout arguments
     int n_items = 0, n_upd = 0;
     RolloutArgs *ra = nullptr;      // [n] device
     UpdateArgs *ua = nullptr;       // [n] device
-    int2 *items = nullptr;          // rollout items (problem, block), longest first
+    int2 *items = nullptr;          // rollout items (problem, block); sized for one group per block
     int2 *upd_items = nullptr;      // update items (problem, step)
     long long *U_off_d = nullptr, *K_off_d = nullptr;
     int *T_d = nullptr;
     Dyn *dyn_d = nullptr;
     uint32_t *counters = nullptr;   // [0] work counter, [1] closed-loop step
     float *cost_scratch = nullptr;
+    float *U_scratch = nullptr;     // packed controls written by the tuner's updates (never read)
     std::vector<void *> owned;
     ~gpmppi_batch() {
         for (void *p : owned) (void)hipFree(p);
@@ -689,9 +694,122 @@ gpmppi_status batch_enqueue_step(gpmppi_batch *b, hipStream_t st) {
     return GPMPPI_OK;
 }
 
+// Most persistent workgroups one compute unit holds at this LDS plan (at most 2).
+int wg_capacity(int precision, int G, int Mpad) {
+    const size_t lds = rollout_lds_bytes(precision, G, Mpad);
+    return std::max(1, std::min(2, (int)((160 * 1024) / (lds + 4096))));
+}
+
+gpmppi_status check_tuning(const gpmppi_tuning *t, int G_max, int wg_max, bool batch) {
+    if (!t) return fail(GPMPPI_E_INVALID, "tuning is NULL");
+    if (t->groups < 1 || t->groups > G_max)
+        return fail(GPMPPI_E_INVALID, "groups must lie in [1, %d] here (got %d)", G_max, t->groups);
+    if (t->rotate != 0 && t->rotate != 1) return fail(GPMPPI_E_INVALID, "rotate must be 0 or 1");
+    if (batch) {
+        if (t->wg_per_cu < 1 || t->wg_per_cu > wg_max)
+            return fail(GPMPPI_E_INVALID, "wg_per_cu must lie in [1, %d] at this shape (got %d)", wg_max,
+                        t->wg_per_cu);
+        if (t->order != 0 && t->order != 1) return fail(GPMPPI_E_INVALID, "order must be 0 or 1");
+    }
+    return GPMPPI_OK;
+}
+
+// Rebuilds the item list and launch grid of a batch for a validated shape.
+gpmppi_status batch_install(gpmppi_batch *b, const gpmppi_tuning &t) {
+    const int B = 32 * t.groups;
+    std::vector<std::pair<double, int2>> it;
+    for (int p = 0; p < b->n; ++p) {
+        const int K = b->ctx[p]->params.K;
+        for (int blk = 0; blk < (K + B - 1) / B; ++blk) it.push_back({b->cost[p], make_int2(p, blk)});
+    }
+    if (t.order == 0)
+        std::stable_sort(it.begin(), it.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+    std::vector<int2> items;
+    for (auto &e : it) items.push_back(e.second);
+    for (int p = 0; p < b->n; ++p) b->ra_h[p].rotate = t.rotate;
+    HIP_TRY(hipMemcpy(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->ra, b->ra_h.data(), sizeof(RolloutArgs) * b->n, hipMemcpyHostToDevice));
+    b->n_items = (int)items.size();
+    b->G = t.groups;
+    b->rotate = t.rotate;
+    b->wg_per_cu = t.wg_per_cu;
+    b->order = t.order;
+    b->grid = std::max(1, std::min(b->n_items, b->cus * t.wg_per_cu));
+    return GPMPPI_OK;
+}
+
+// Mean time in ms of reps launches of fn after one warm-up, on stream st.
+template <typename F>
+gpmppi_status time_launches(F &&fn, int reps, hipStream_t st, double &ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GPMPPI_E_HIP, "hipEventCreate failed");
+    }
+    gpmppi_status r = fn();
+    if (r == GPMPPI_OK && hipEventRecord(e0, st) != hipSuccess) r = fail(GPMPPI_E_HIP, "hipEventRecord failed");
+    for (int i = 0; i < reps && r == GPMPPI_OK; ++i) r = fn();
+    if (r == GPMPPI_OK && hipEventRecord(e1, st) != hipSuccess) r = fail(GPMPPI_E_HIP, "hipEventRecord failed");
+    float t = 0.0f;
+    if (r == GPMPPI_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        r = fail(GPMPPI_E_HIP, "event timing failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ms = (double)t / reps;
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
+
+gpmppi_status gpmppi_set_tuning(gpmppi_ctx *c, const gpmppi_tuning *t) {
+    g_last_error.clear();
+    if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
+    gpmppi_status st = check_tuning(t, rollout_groups(c->params.precision, c->Mpad), 2, false);
+    if (st != GPMPPI_OK) return st;
+    c->groups = t->groups;
+    c->rotate = t->rotate;
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_get_tuning(const gpmppi_ctx *c, gpmppi_tuning *t) {
+    g_last_error.clear();
+    if (!c || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
+    *t = gpmppi_tuning{c->groups, c->rotate, 1, 0, 0.0};
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
+                          gpmppi_tuning *chosen, void *stream) {
+    g_last_error.clear();
+    if (!c || !x0_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
+    hipStream_t st = (hipStream_t)stream;
+    const int G_max = rollout_groups(c->params.precision, c->Mpad);
+    const int keep_groups = c->groups, keep_rotate = c->rotate;
+    gpmppi_tuning best{c->groups, c->rotate, 1, 0, -1.0};
+    for (int G = 1; G <= G_max; ++G)
+        for (int rot = 0; rot <= 1; ++rot) {
+            c->groups = G;
+            c->rotate = rot;
+            double ms = 0.0;
+            gpmppi_status r = time_launches(
+                [&]() { return gpmppi_rollout(c, x0_d, U_d, seed, c->cost_scratch, nullptr, stream); }, reps, st,
+                ms);
+            if (r != GPMPPI_OK) {
+                c->groups = keep_groups;
+                c->rotate = keep_rotate;
+                return r;
+            }
+            if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, ms};
+        }
+    c->groups = best.groups;
+    c->rotate = best.rotate;
+    if (chosen) *chosen = best;
+    return GPMPPI_OK;
+}
 
 gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const gpmppi_gp gp[],
                                 const gpmppi_obstacles obstacles[], const gpmppi_path paths[], gpmppi_batch **out) {
@@ -724,32 +842,26 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
         b->U_off[p + 1] = b->U_off[p] + 2LL * params[p].T;
         b->K_off[p + 1] = b->K_off[p] + params[p].K;
         b->Mpad_max = std::max(b->Mpad_max, c->Mpad);
+        // one sample block's work: T steps of the triangular W walk, kernel vectors and world
+        b->cost.push_back((double)params[p].T * ((double)c->Mpad * c->Mpad + 16.0 * c->Mpad +
+                                                 (double)c->geo.P + 2.0 * c->n_obs + 200.0));
     }
-    b->G = 2;
-    for (gpmppi_ctx *c : b->ctx) b->G = std::min(b->G, rollout_groups(b->precision, c->Mpad));
-    b->G = std::min(b->G, rollout_groups(b->precision, b->Mpad_max));
-    const int B = 32 * b->G;
-    // items: (problem, sample block), longest first (estimated cost)
-    std::vector<std::pair<double, int2>> it;
+    // every problem runs at the LDS plan of the largest M
+    b->G_max = rollout_groups(b->precision, b->Mpad_max);
+    long long max_items = 0, n_upd = 0;
     std::vector<int2> upd;
     for (int p = 0; p < n; ++p) {
-        const gpmppi_ctx *c = b->ctx[p];
-        const double cost = (double)params[p].T * ((double)c->Mpad * c->Mpad + 16.0 * c->Mpad +
-                                                    (double)c->geo.P + 2.0 * c->n_obs + 200.0);
-        for (int blk = 0; blk < (params[p].K + B - 1) / B; ++blk) it.push_back({cost, make_int2(p, blk)});
+        max_items += (params[p].K + 31) / 32;
         for (int k = 0; k < params[p].T; ++k) upd.push_back(make_int2(p, k));
     }
-    std::stable_sort(it.begin(), it.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
-    std::vector<int2> items;
-    for (auto &e : it) items.push_back(e.second);
-    b->n_items = (int)items.size();
-    b->n_upd = (int)upd.size();
-    std::vector<RolloutArgs> ra(n);
+    n_upd = (long long)upd.size();
+    b->n_upd = (int)n_upd;
     std::vector<UpdateArgs> ua(n);
     std::vector<int> T(n);
     std::vector<Dyn> dyn(n);
+    b->ra_h.resize(n);
     for (int p = 0; p < n; ++p) {
-        ra[p] = rollout_args(b->ctx[p], nullptr, nullptr, 0, nullptr, nullptr, nullptr);
+        b->ra_h[p] = rollout_args(b->ctx[p], nullptr, nullptr, 0, nullptr, nullptr, nullptr);
         ua[p] = update_args(b->ctx[p], nullptr, nullptr, 0, nullptr, nullptr, nullptr);
         T[p] = params[p].T;
         dyn[p] = b->ctx[p]->dyn;
@@ -761,7 +873,7 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
     };
     b->ra = track(dev_alloc<RolloutArgs>(n, st));
     b->ua = track(dev_alloc<UpdateArgs>(n, st));
-    b->items = track(dev_alloc<int2>(items.size(), st));
+    b->items = track(dev_alloc<int2>((size_t)max_items, st));
     b->upd_items = track(dev_alloc<int2>(upd.size(), st));
     b->U_off_d = track(dev_alloc<long long>(n + 1, st));
     b->K_off_d = track(dev_alloc<long long>(n + 1, st));
@@ -769,6 +881,7 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
     b->dyn_d = track(dev_alloc<Dyn>(n, st));
     b->counters = track(dev_alloc<uint32_t>(4, st));
     b->cost_scratch = track(dev_alloc<float>((size_t)b->K_off[n], st));
+    b->U_scratch = track(dev_alloc<float>((size_t)b->U_off[n], st));
     if (st != GPMPPI_OK) {
         delete b;
         return st;
@@ -778,9 +891,7 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
         delete b;                                                                             \
         return fail(GPMPPI_E_HIP, "upload of the batch tables failed");                       \
     }
-    UP(b->ra, ra.data(), sizeof(RolloutArgs) * n);
     UP(b->ua, ua.data(), sizeof(UpdateArgs) * n);
-    UP(b->items, items.data(), sizeof(int2) * items.size());
     UP(b->upd_items, upd.data(), sizeof(int2) * upd.size());
     UP(b->U_off_d, b->U_off.data(), sizeof(long long) * (n + 1));
     UP(b->K_off_d, b->K_off.data(), sizeof(long long) * (n + 1));
@@ -791,14 +902,73 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
         delete b;
         return fail(GPMPPI_E_HIP, "hipMemset failed");
     }
-    // persistent grid: every CU times the workgroups it can hold at this LDS size
-    int dev = 0, cus = 0;
+    int dev = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const size_t lds = rollout_lds_bytes(b->precision, b->Mpad_max);
-    const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / (lds + 4096))));
-    b->grid = std::max(1, std::min(b->n_items, std::max(1, cus) * per_cu));
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->cus = std::max(1, b->cus);
+    b->wg_per_cu_max = wg_capacity(b->precision, b->G_max, b->Mpad_max);
+    if ((st = batch_install(b, gpmppi_tuning{b->G_max, 1, b->wg_per_cu_max, 0, 0.0})) != GPMPPI_OK) {
+        delete b;
+        return st;
+    }
     *out = b;
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t) {
+    g_last_error.clear();
+    if (!b) return fail(GPMPPI_E_INVALID, "batch is NULL");
+    gpmppi_status st = check_tuning(t, b->G_max, t ? wg_capacity(b->precision, t->groups, b->Mpad_max) : 1, true);
+    if (st != GPMPPI_OK) return st;
+    return batch_install(b, *t);
+}
+
+gpmppi_status gpmppi_batch_get_tuning(const gpmppi_batch *b, gpmppi_tuning *t) {
+    g_last_error.clear();
+    if (!b || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
+    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, 0.0};
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
+                                gpmppi_tuning *chosen, void *stream) {
+    g_last_error.clear();
+    if (!b || !x0_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
+    hipStream_t st = (hipStream_t)stream;
+    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, 0.0};
+    gpmppi_tuning best{0, 0, 0, 0, -1.0};
+    for (int G = 1; G <= b->G_max; ++G) {
+        const int wmax = wg_capacity(b->precision, G, b->Mpad_max);
+        for (int rot = 0; rot <= 1; ++rot)
+            for (int w = 1; w <= wmax; ++w)
+                for (int ord = 0; ord <= 1; ++ord) {
+                    const gpmppi_tuning cand{G, rot, w, ord, 0.0};
+                    gpmppi_status r = batch_install(b, cand);
+                    double ms = 0.0;
+                    if (r == GPMPPI_OK) {
+                        const BatchPtrs q{x0_d, U_d, b->U_scratch, b->cost_scratch, nullptr, seed, nullptr,
+                                          b->U_off_d, b->K_off_d};
+                        r = time_launches(
+                            [&]() -> gpmppi_status {
+                                HIP_TRY(launch_batch_patch(b->ra, b->ua, b->n, q, st));
+                                HIP_TRY(launch_counter_reset(b->counters, st));
+                                HIP_TRY(launch_rollout_batch(b->ra, b->items, b->n_items, b->counters,
+                                                             b->precision, b->G, b->Mpad_max, b->grid, st));
+                                return GPMPPI_OK;
+                            },
+                            reps, st, ms);
+                    }
+                    if (r != GPMPPI_OK) {
+                        (void)batch_install(b, keep);
+                        return r;
+                    }
+                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, ms};
+                }
+    }
+    gpmppi_status r = batch_install(b, best);
+    if (r != GPMPPI_OK) return r;
+    if (chosen) *chosen = best;
     return GPMPPI_OK;
 }
 

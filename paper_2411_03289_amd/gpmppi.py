@@ -63,6 +63,14 @@ class gpmppi_trace(ctypes.Structure):
                                               "lane_margin_d", "obs_margin_d", "u_d")]
 
 
+class gpmppi_tuning(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("rotate", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -97,6 +105,12 @@ def lib() -> ctypes.CDLL:
         "gpmppi_batch_layout": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "gpmppi_batch_step": [vp, vp, vp, u64, vp, vp, vp, vp],
         "gpmppi_batch_closed_loop": [vp, vp, vp, u64, i32, f64, vp, i32, vp],
+        "gpmppi_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
+        "gpmppi_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
+        "gpmppi_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
+        "gpmppi_batch_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
+        "gpmppi_batch_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
+        "gpmppi_batch_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -425,6 +439,42 @@ def gpmppi_batch_closed_loop(b: Batch, x, U, seed0: int, n_steps: int, amplitude
                                           ctypes.c_uint64(seed0), int(n_steps), float(amplitude),
                                           _dev(x_hist, 5 * b.n * (n_steps + 1), "x_hist", optional=True),
                                           int(bool(use_graph)), _stream(stream)))
+
+
+def gpmppi_tune(ctx: Context, x0, U, seed: int, reps: int = 3, stream=None) -> dict:
+    t = gpmppi_tuning()
+    _check(lib().gpmppi_tune(ctx.handle, _dev(x0, 5, "x0"), _dev(U, 2 * ctx.params["T"], "U"),
+                             ctypes.c_uint64(seed), int(reps), ctypes.byref(t), _stream(stream)))
+    return t.as_dict()
+
+
+def gpmppi_set_tuning(ctx: Context, groups: int, rotate: int, wg_per_cu: int = 1, order: int = 0):
+    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, 0.0)
+    _check(lib().gpmppi_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def gpmppi_get_tuning(ctx: Context) -> dict:
+    t = gpmppi_tuning()
+    _check(lib().gpmppi_get_tuning(ctx.handle, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def gpmppi_batch_tune(b: Batch, x0, U, seed: int, reps: int = 2, stream=None) -> dict:
+    t = gpmppi_tuning()
+    _check(lib().gpmppi_batch_tune(b.handle, _dev(x0, 5 * b.n, "x0"), _dev(U, b.U_off[-1], "U"),
+                                   ctypes.c_uint64(seed), int(reps), ctypes.byref(t), _stream(stream)))
+    return t.as_dict()
+
+
+def gpmppi_batch_set_tuning(b: Batch, groups: int, rotate: int, wg_per_cu: int, order: int):
+    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, 0.0)
+    _check(lib().gpmppi_batch_set_tuning(b.handle, ctypes.byref(t)))
+
+
+def gpmppi_batch_get_tuning(b: Batch) -> dict:
+    t = gpmppi_tuning()
+    _check(lib().gpmppi_batch_get_tuning(b.handle, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def gpmppi_batch_destroy(b: Batch):

@@ -96,3 +96,44 @@ def test_batch_closed_loop_graph_equals_eager_and_single_problem_loops():
         t.cuda.synchronize()
         np.testing.assert_array_equal(h.cpu().numpy().reshape(n + 1, 5), xh[:, i])
         np.testing.assert_array_equal(Ud.cpu().numpy(), runs[0][1][U_off[i]:U_off[i + 1]])
+
+
+def test_batch_autotuner_choice_keeps_results_of_the_matching_single_shape():
+    t = torch()
+    ps = _problems()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    U_off, K_off = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    seed = 91
+    chosen = B.gpmppi_batch_tune(b, dev(x0), dev(U), seed, reps=1)
+    print("batch tuning", chosen, flush=True)
+    assert chosen["groups"] in (1, 2) and chosen["rotate"] in (0, 1) and chosen["wg_per_cu"] in (1, 2)
+    assert chosen["order"] in (0, 1) and chosen["ms"] > 0
+    got = B.gpmppi_batch_get_tuning(b)
+    assert {k: got[k] for k in ("groups", "rotate", "wg_per_cu", "order")} == \
+        {k: chosen[k] for k in ("groups", "rotate", "wg_per_cu", "order")}
+    # the schedule (order, occupancy) never changes a result; the shape (groups, rotate)
+    # selects the same grouping of partial sums as a single context set to it
+    outs = []
+    for wg, order in ((1, 1), (chosen["wg_per_cu"], chosen["order"])):
+        B.gpmppi_batch_set_tuning(b, chosen["groups"], chosen["rotate"], wg, order)
+        Uo = t.empty(U_off[-1], device="cuda")
+        costs = t.empty(K_off[-1], device="cuda")
+        B.gpmppi_batch_step(b, dev(x0), dev(U), seed, Uo, costs)
+        t.cuda.synchronize()
+        outs.append((Uo.cpu().numpy(), costs.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    for i, p in enumerate(ps):
+        ctx = B.gpmppi_init(p, B.FP32)
+        B.gpmppi_set_tuning(ctx, chosen["groups"], chosen["rotate"])
+        U1, S1, _ = gpu_step(p, B.FP32, seed=seed, ctx=ctx)
+        np.testing.assert_array_equal(outs[0][1][K_off[i]:K_off[i + 1]].astype(np.float64), S1)
+        np.testing.assert_array_equal(outs[0][0][U_off[i]:U_off[i + 1]].reshape(-1, 2).astype(np.float64), U1)
+
+
+def test_batch_tuning_rejects_inadmissible_shapes():
+    b = B.gpmppi_batch_init(_problems(), B.FP32)
+    for bad in ((0, 1, 1, 0), (3, 1, 1, 0), (1, 2, 1, 0), (1, 1, 0, 0), (1, 1, 3, 0), (1, 1, 1, 2)):
+        with pytest.raises(B.GpmppiError):
+            B.gpmppi_batch_set_tuning(b, *bad)

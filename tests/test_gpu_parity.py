@@ -365,3 +365,25 @@ def test_terrain_means_feed_the_weight_estimate():
     np.testing.assert_allclose(w, [0, 0, 1], atol=1e-6)
     np.testing.assert_allclose(w, TR.solve_weights(Yv, Yw, F[:, :, 0], F[:, :, 1], np.full(3, 1 / 3), 0.0),
                                atol=1e-6)
+
+
+def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
+    t = torch()
+    pr = W.make_config(0, K=300, T=12)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    for groups in (1, 2):
+        for rotate in (0, 1):
+            B.gpmppi_set_tuning(ctx, groups, rotate)
+            assert B.gpmppi_get_tuning(ctx)["groups"] == groups
+            S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+            _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"shape groups={groups} rotate={rotate}")
+            S_g2, _ = gpu_rollout(pr, ctx=ctx)
+            np.testing.assert_array_equal(S_g, S_g2)
+    chosen = B.gpmppi_tune(ctx, dev(pr.x0), dev(pr.U0), pr.seed, reps=2)
+    print("tuning", chosen, flush=True)
+    got = B.gpmppi_get_tuning(ctx)
+    assert (got["groups"], got["rotate"]) == (chosen["groups"], chosen["rotate"]) and chosen["ms"] > 0
+    for bad in ((0, 1), (3, 0), (1, 5)):
+        with pytest.raises(B.GpmppiError):
+            B.gpmppi_set_tuning(ctx, *bad)
