@@ -34,6 +34,16 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 FORMS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 U_ERR_BAR = 1e-3
 
+# HBM bytes per rollout launch at this workload: rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (factors from a 1 GiB device copy in the same runs), taken
+# on the kernel sources whose SHA-256 is given; reported only while they match.
+KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd/csrc/device_common.hpp",
+                  "paper_2411_03289_amd/csrc/kernels.hpp", "paper_2411_03289_amd/build.py"]
+MEASURED_TRAFFIC = {
+    "sources_sha256": "cf634db2e466e4a69501c7346365f6cf15381a1891cc3e23858399a675ee3d98",
+    "bytes": {"fp32": 578524 * 1024, "bf16x3": 545444 * 1024, "bf16": 18229 * 1024},
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -60,13 +70,24 @@ def cpu_baseline(pr, n_samples):
                       f"FP64 NumPy/SciPy, {dt:.1f} s wall"}
 
 
+def measured_traffic(form):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != MEASURED_TRAFFIC["sources_sha256"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"].get(form)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="fp32,bf16x3,bf16")
-    ap.add_argument("--cpu-samples", type=int, default=4096)
+    ap.add_argument("--cpu-samples", type=int, default=2048)
     ap.add_argument("--copy-calibrate-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -162,7 +183,7 @@ def main():
         "config": {"workload": "GP-MPPI iteration K=16384 T=100 M=1024 (2 outputs, d=4), 50 obstacles, "
                                "figure-eight P=256", "form": best, "K": K, "T": T, "M": M},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(best), "traffic_unit": "bytes per launch",
                      "kernel": "rollout_kernel", "flops_per_launch": flops_per_launch},
         "forms": results,
         "speedup_vs_fp32": {n: results["fp32"]["ms_per_step"] / results[n]["ms_per_step"]

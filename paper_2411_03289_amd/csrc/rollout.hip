@@ -215,26 +215,30 @@ __host__ __device__ constexpr int staged_slots(int Mpad) {
     return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : Mpad + (Mpad >> 1);
 }
 
+// Native vectors (not HIP's float4 struct, whose copies become memcpy of a
+// private array that the compiler keeps in scratch memory).
 struct StagedInputs {
-    float4 v[6];
+    v4f v[6];
 };
 
 template <int PREC>
 __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
     const int Mpad = g.Mpad, nz = Mpad, ns = staged_slots<PREC>(Mpad);
-    const float4 *zsrc, *asrc;
+    const v4f *zsrc, *asrc;
     if constexpr (PREC == GPMPPI_FP32) {
-        zsrc = reinterpret_cast<const float4 *>(g.zs) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const float4 *>(g.alpha + (size_t)o * Mpad);
+        zsrc = reinterpret_cast<const v4f *>(g.zs) + (size_t)o * Mpad;
+        asrc = reinterpret_cast<const v4f *>(g.alpha + (size_t)o * Mpad);
     } else {
-        zsrc = reinterpret_cast<const float4 *>(g.zs2) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const float4 *>(g.cza + (size_t)o * Mpad * 2);
+        zsrc = reinterpret_cast<const v4f *>(g.zs2) + (size_t)o * Mpad;
+        asrc = reinterpret_cast<const v4f *>(g.cza + (size_t)o * Mpad * 2);
     }
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
         const int slot = threadIdx.x + r * kThreads;
-        if (slot < nz) st.v[r] = zsrc[slot];
-        else if (slot < ns) st.v[r] = asrc[slot - nz];
+        v4f val = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (slot < nz) val = zsrc[slot];
+        else if (slot < ns) val = asrc[slot - nz];
+        st.v[r] = val;
     }
 }
 
@@ -242,7 +246,7 @@ template <int PREC>
 __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev &g, unsigned char *lds,
                                             size_t zs_off) {
     const int ns = staged_slots<PREC>(g.Mpad);
-    float4 *dst = reinterpret_cast<float4 *>(lds + zs_off);
+    v4f *dst = reinterpret_cast<v4f *>(lds + zs_off);
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
         const int slot = threadIdx.x + r * kThreads;

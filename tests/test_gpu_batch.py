@@ -95,7 +95,7 @@ def test_batch_closed_loop_graph_equals_eager_and_single_problem_loops():
         B.gpmppi_closed_loop(ctx, xd, Ud, ps[0].seed, n, 0.3, h)
         t.cuda.synchronize()
         np.testing.assert_array_equal(h.cpu().numpy().reshape(n + 1, 5), xh[:, i])
-        np.testing.assert_array_equal(Ud.cpu().numpy(), runs[0][1][U_off[i]:U_off[i + 1]])
+        np.testing.assert_array_equal(Ud.cpu().numpy().reshape(-1), runs[0][1][U_off[i]:U_off[i + 1]])
 
 
 def test_batch_autotuner_choice_keeps_results_of_the_matching_single_shape():
