@@ -208,6 +208,32 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *ctx, float *x_d, float *U_d, uint64
                                  double amplitude, float *x_hist_d, float *U0_hist_d,
                                  int32_t use_graph, void *stream);
 
+/* ------------------------------------------------------------------ differentiation form
+ * Gradient of the smoothed expected cost
+ *     J(U, log_ell, log_sf) = (1/K) sum_s S~^s,
+ * S~ being the rollout cost of gpmppi_rollout (Alg. 1 Step 1, Eqs. 1-3 and
+ * 10-16, Eq. 5's sum) with the lane-exit indicator replaced by
+ * sigmoid((d_lane - r_bar) / tau) and the collision indicator by
+ * sigmoid(-min_j d_bar_j / tau) (tau in metres), with respect to the nominal
+ * controls U, the log length-scales [2][4] and the log signal deviations [2] of
+ * the two GPs.  The noise is fixed by the seed (common random numbers); the
+ * derivative of clip(U + eps) is 1 strictly inside the box and 0 outside; the
+ * hyperparameter derivative is total (through the kernel vectors, alpha and
+ * (K(Z, Z) + sn^2 I)^-1).  The adjoint rollout stores the state every
+ * checkpoint_every steps (in [1, T]) and recomputes each segment before
+ * reversing it; results do not depend on checkpoint_every.
+ * FP32 on the GPU, whatever the context's precision.  Needs M <= 512, no
+ * terrain ensemble, no goal terms and no Step-2 tightening
+ * (GPMPPI_E_UNSUPPORTED otherwise).
+ * x0_d [5], U_d [T][2] device; outputs (device): J_d [1], dU_d [T][2],
+ * dlog_ell_d [2][4], dlog_sf_d [2], costs_d [K] the smoothed per-sample costs
+ * (may be NULL).  A workspace of about 8 T K Mpad bytes (the r = A^-1 k rows of
+ * every sample and step) is allocated on first use and kept by the context
+ * (GPMPPI_E_NOMEM if that fails).  Enqueued on stream. */
+gpmppi_status gpmppi_grad(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, double tau,
+                          int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
+                          float *costs_d, void *stream);
+
 /* ------------------------------------------------------------------ launch shapes
  * The rollout's launch shape, chosen per context (or batch) by measurement.
  * None of these changes what is computed; they change the grouping of the

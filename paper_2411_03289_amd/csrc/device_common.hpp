@@ -50,16 +50,20 @@ struct NoiseParams {
     float umin0, umin1, umax0, umax1;
 };
 
-__device__ __forceinline__ float2 sampled_control(const NoiseParams &np, int k, int s, float U0,
-                                                  float U1) {
+// U_k + eps_k^s before the clip.
+__device__ __forceinline__ float2 sampled_raw(const NoiseParams &np, int k, int s, float U0, float U1) {
     const uint4 w = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)s, np.pid, 0u), np.key0, np.key1);
     const float u1 = uniform_open(w.x), u2 = uniform_open(w.y);
     const float r = sqrtf(-2.0f * logf(u1));
     float sn, cs;
     sincospif(2.0f * u2, &sn, &cs);
-    const float a = fminf(fmaxf(U0 + np.sig_v * (r * cs), np.umin0), np.umax0);
-    const float b = fminf(fmaxf(U1 + np.sig_w * (r * sn), np.umin1), np.umax1);
-    return make_float2(a, b);
+    return make_float2(U0 + np.sig_v * (r * cs), U1 + np.sig_w * (r * sn));
+}
+
+__device__ __forceinline__ float2 sampled_control(const NoiseParams &np, int k, int s, float U0,
+                                                  float U1) {
+    const float2 raw = sampled_raw(np, k, s, U0, U1);
+    return make_float2(fminf(fmaxf(raw.x, np.umin0), np.umax0), fminf(fmaxf(raw.y, np.umin1), np.umax1));
 }
 
 // Round-to-nearest-even float -> bfloat16 bits (finite inputs).

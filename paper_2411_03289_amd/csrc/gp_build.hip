@@ -208,6 +208,45 @@ hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, Terrain
     return hipGetLastError();
 }
 
+// Q = W^T W = A^-1 (FP64) into Qd, for the adjoint's r = Q k; one thread
+// per entry, the sum running over the rows k >= max(i, j) where W is nonzero.
+__global__ void qmat_kernel(const double *W, int Mpad, double *Qd) {
+    const int j = blockIdx.x * 16 + threadIdx.x;
+    const int i = blockIdx.y * 16 + threadIdx.y;
+    if (i >= Mpad || j >= Mpad) return;
+    double acc = 0.0;
+    for (int k = (i > j ? i : j); k < Mpad; ++k) acc += W[(size_t)k * Mpad + i] * W[(size_t)k * Mpad + j];
+    Qd[(size_t)i * Mpad + j] = acc;
+}
+
+// Dense FP32 packing of Q in the matrix-core operand order of the FP32 W
+// blocks: block b = t NT + it, float4 [b][q][lane], component c holds
+// Q[32t + l%32][32 it + 2(4q+c) + l/32].  Rows/columns beyond M are zero.
+__global__ void pack_q_kernel(const double *Qd, int M, int Mpad, float4 *q32) {
+    const int blk = blockIdx.x, lane = threadIdx.x;
+    const int NT = Mpad / 32;
+    const int t = blk / NT, it = blk % NT;
+    const int i = 32 * t + (lane & 31);
+    const int half = lane >> 5;
+    auto qval = [&](int j) -> float { return (i < M && j < M) ? (float)Qd[(size_t)i * Mpad + j] : 0.0f; };
+    for (int q = 0; q < 4; ++q) {
+        float4 v;
+        v.x = qval(32 * it + 2 * (4 * q + 0) + half);
+        v.y = qval(32 * it + 2 * (4 * q + 1) + half);
+        v.z = qval(32 * it + 2 * (4 * q + 2) + half);
+        v.w = qval(32 * it + 2 * (4 * q + 3) + half);
+        q32[(size_t)blk * 256 + q * 64 + lane] = v;
+    }
+}
+
+hipError_t pack_q(const GpBuildBuffers &b, int M, int Mpad, float4 *q32, hipStream_t st) {
+    // A (the Cholesky factor's storage) is free once W has been formed
+    hipLaunchKernelGGL(qmat_kernel, dim3(Mpad / 16, Mpad / 16), dim3(16, 16), 0, st, b.W, Mpad, b.A);
+    const int NT = Mpad / 32;
+    hipLaunchKernelGGL(pack_q_kernel, dim3(NT * NT), dim3(64), 0, st, b.A, M, Mpad, q32);
+    return hipGetLastError();
+}
+
 // Terrain means at n queries: out[q][i][o] = k_o(q)^T alpha_{o,i}; one
 // workgroup per query, threads over training points, FP64 accumulation of the
 // FP32 kernel values.  alpha_terr is [2][n_terr][Mpad] FP64.

@@ -1,0 +1,896 @@
+// Adjoint rollout on gfx950: gradient of the smoothed expected cost
+//   J(U, log ell, log sf) = (1/K) sum_s S~^s
+// where S~ is the rollout cost of Alg. 1 Step 1 (Eqs. 1-3, 10-16, one
+// combined stage cost) with the lane-exit and collision indicators replaced by
+// sigmoid((d_lane - r_bar)/tau) and sigmoid(-min_j d_bar_j / tau).  The noise
+// is fixed by the seed; u = clip(U + eps) has derivative 1 strictly inside the
+// box.  The derivative in the GP hyperparameters is total (through k, alpha and
+// A^-1, A = K(Z, Z) + sn^2 I).
+//
+// grad_kernel: one workgroup of 256 threads per 32 samples (one 32-column
+// matrix-core group; 8 loop parts = 4 waves x 2 half-waves).
+//   job 0   forward over all T steps: costs, and the state (x, Sigma) every C
+//           steps (checkpoints);
+//   job j   for segment n - j (last first): recompute the segment's C steps
+//           from its checkpoint, keeping per-step state, controls, GP means
+//           and variances in a scratch array, then step backwards through it.
+// Both passes run the same forward code, so the recomputed trajectory is the
+// first pass's bit for bit.  Per backward step, per sample, in registers: the
+// adjoints of the stage cost, of Sigma+ = A Sigma A^T + dt^2 diag(s2) (the
+// 15 stored entries as independent scalars), of the Euler step and of the
+// Jacobian A(theta, v).  Per output o, for the whole block: the kernel vector
+// k (VALU) and r = Q k with Q = A^-1 = W^T W (dense 32x32 FP32 tiles on the
+// matrix cores); with beta_j = k_j (-mbar alpha_j + 2 s2bar r_j):
+//   dq_d        = 2 ln2 s_d sum_j beta_j (qs_d - zs_jd)
+//   d log ell_d = -2 ln2 sum_j beta_j (qs_d - zs_jd)^2       (through k)
+//   d log sf    = -2 sum_j beta_j + 2 sf^2 s2bar             (through k, sf^2)
+// and the dependence through A: sum_ij (P_ij - b_i alpha_j) dA_ij/dtheta with
+// b = sum mbar r and P = sum s2bar r r^T over all sample-steps.  b is summed in
+// registers; P is formed by grad_syrk_kernel from the stored r (FP32
+// [T K][Mpad] per output) and contracted on the fly with dA/dtheta.
+#include "gp_tiles.hpp"
+
+namespace gpmppi {
+
+namespace {
+
+constexpr int kB = 32;           // samples per workgroup
+constexpr int kParts = 8;        // loop splitters
+constexpr int kSegF = 28;        // per step: x 5, p 15, u 2, m 2, s2 2, latent-positive flags 2
+constexpr int kCkF = 20;         // per checkpoint: x 5, p 15
+constexpr float kLn2 = 0.69314718055994531f;
+
+// p index: 00 01 02 03 04 11 12 13 14 22 23 24 33 34 44
+struct Jac {
+    float a02, a03, a12, a13;
+};
+
+__device__ __forceinline__ void cov_forward(const float p[15], const Jac &J, float a24, float a33, float a44,
+                                            float e3, float e4, float P[15]) {
+    const float p00 = p[0], p01 = p[1], p02 = p[2], p03 = p[3], p04 = p[4], p11 = p[5], p12 = p[6], p13 = p[7],
+                p14 = p[8], p22 = p[9], p23 = p[10], p24 = p[11], p33 = p[12], p34 = p[13], p44 = p[14];
+    const float b00 = p00 + J.a02 * p02 + J.a03 * p03, b01 = p01 + J.a02 * p12 + J.a03 * p13,
+                b02 = p02 + J.a02 * p22 + J.a03 * p23, b03 = p03 + J.a02 * p23 + J.a03 * p33,
+                b04 = p04 + J.a02 * p24 + J.a03 * p34;
+    const float b11 = p11 + J.a12 * p12 + J.a13 * p13, b12 = p12 + J.a12 * p22 + J.a13 * p23,
+                b13 = p13 + J.a12 * p23 + J.a13 * p33, b14 = p14 + J.a12 * p24 + J.a13 * p34;
+    const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
+    const float b33 = a33 * p33, b34 = a33 * p34, b44 = a44 * p44;
+    P[0] = b00 + J.a02 * b02 + J.a03 * b03;
+    P[1] = b01 + J.a12 * b02 + J.a13 * b03;
+    P[2] = b02 + a24 * b04;
+    P[3] = a33 * b03;
+    P[4] = a44 * b04;
+    P[5] = b11 + J.a12 * b12 + J.a13 * b13;
+    P[6] = b12 + a24 * b14;
+    P[7] = a33 * b13;
+    P[8] = a44 * b14;
+    P[9] = b22 + a24 * b24;
+    P[10] = a33 * b23;
+    P[11] = a44 * b24;
+    P[12] = a33 * b33 + e3;
+    P[13] = a44 * b34;
+    P[14] = a44 * b44 + e4;
+}
+
+// Reverse of cov_forward: Pb (adjoint of P) -> pb (adjoint of p, overwritten),
+// adjoints of a02 a03 a12 a13 added to Jb, of e3 and e4 returned.
+__device__ __forceinline__ void cov_backward(const float p[15], const Jac &J, float a24, float a33, float a44,
+                                             const float Pb[15], float pb[15], Jac &Jb, float &e3b, float &e4b) {
+    const float p02 = p[2], p03 = p[3], p12 = p[6], p13 = p[7], p22 = p[9], p23 = p[10], p24 = p[11], p33 = p[12],
+                p34 = p[13];
+    // forward intermediates needed by the reverse
+    const float b02 = p02 + J.a02 * p22 + J.a03 * p23, b03 = p03 + J.a02 * p23 + J.a03 * p33;
+    const float b12 = p12 + J.a12 * p22 + J.a13 * p23, b13 = p13 + J.a12 * p23 + J.a13 * p33;
+    float bb00 = 0, bb01 = 0, bb02 = 0, bb03 = 0, bb04 = 0, bb11 = 0, bb12 = 0, bb13 = 0, bb14 = 0, bb22 = 0,
+          bb23 = 0, bb24 = 0, bb33 = 0, bb34 = 0, bb44 = 0;
+    // P00 = b00 + a02 b02 + a03 b03
+    bb00 += Pb[0]; bb02 += J.a02 * Pb[0]; bb03 += J.a03 * Pb[0];
+    Jb.a02 += b02 * Pb[0]; Jb.a03 += b03 * Pb[0];
+    // P01 = b01 + a12 b02 + a13 b03
+    bb01 += Pb[1]; bb02 += J.a12 * Pb[1]; bb03 += J.a13 * Pb[1];
+    Jb.a12 += b02 * Pb[1]; Jb.a13 += b03 * Pb[1];
+    // P02 = b02 + a24 b04; P03 = a33 b03; P04 = a44 b04
+    bb02 += Pb[2]; bb04 += a24 * Pb[2];
+    bb03 += a33 * Pb[3];
+    bb04 += a44 * Pb[4];
+    // P11 = b11 + a12 b12 + a13 b13
+    bb11 += Pb[5]; bb12 += J.a12 * Pb[5]; bb13 += J.a13 * Pb[5];
+    Jb.a12 += b12 * Pb[5]; Jb.a13 += b13 * Pb[5];
+    // P12 = b12 + a24 b14; P13 = a33 b13; P14 = a44 b14
+    bb12 += Pb[6]; bb14 += a24 * Pb[6];
+    bb13 += a33 * Pb[7];
+    bb14 += a44 * Pb[8];
+    // P22 = b22 + a24 b24; P23 = a33 b23; P24 = a44 b24
+    bb22 += Pb[9]; bb24 += a24 * Pb[9];
+    bb23 += a33 * Pb[10];
+    bb24 += a44 * Pb[11];
+    // P33 = a33 b33 + e3; P34 = a44 b34; P44 = a44 b44 + e4
+    bb33 += a33 * Pb[12]; e3b = Pb[12];
+    bb34 += a44 * Pb[13];
+    bb44 += a44 * Pb[14]; e4b = Pb[14];
+    // b rows -> p
+    float q[15] = {};
+    // b00 = p00 + a02 p02 + a03 p03
+    q[0] += bb00; q[2] += J.a02 * bb00; q[3] += J.a03 * bb00; Jb.a02 += p02 * bb00; Jb.a03 += p03 * bb00;
+    // b01 = p01 + a02 p12 + a03 p13
+    q[1] += bb01; q[6] += J.a02 * bb01; q[7] += J.a03 * bb01; Jb.a02 += p12 * bb01; Jb.a03 += p13 * bb01;
+    // b02 = p02 + a02 p22 + a03 p23
+    q[2] += bb02; q[9] += J.a02 * bb02; q[10] += J.a03 * bb02; Jb.a02 += p22 * bb02; Jb.a03 += p23 * bb02;
+    // b03 = p03 + a02 p23 + a03 p33
+    q[3] += bb03; q[10] += J.a02 * bb03; q[12] += J.a03 * bb03; Jb.a02 += p23 * bb03; Jb.a03 += p33 * bb03;
+    // b04 = p04 + a02 p24 + a03 p34
+    q[4] += bb04; q[11] += J.a02 * bb04; q[13] += J.a03 * bb04; Jb.a02 += p24 * bb04; Jb.a03 += p34 * bb04;
+    // b11 = p11 + a12 p12 + a13 p13
+    q[5] += bb11; q[6] += J.a12 * bb11; q[7] += J.a13 * bb11; Jb.a12 += p12 * bb11; Jb.a13 += p13 * bb11;
+    // b12 = p12 + a12 p22 + a13 p23
+    q[6] += bb12; q[9] += J.a12 * bb12; q[10] += J.a13 * bb12; Jb.a12 += p22 * bb12; Jb.a13 += p23 * bb12;
+    // b13 = p13 + a12 p23 + a13 p33
+    q[7] += bb13; q[10] += J.a12 * bb13; q[12] += J.a13 * bb13; Jb.a12 += p23 * bb13; Jb.a13 += p33 * bb13;
+    // b14 = p14 + a12 p24 + a13 p34
+    q[8] += bb14; q[11] += J.a12 * bb14; q[13] += J.a13 * bb14; Jb.a12 += p24 * bb14; Jb.a13 += p34 * bb14;
+    // b22 = p22 + a24 p24; b23 = p23 + a24 p34; b24 = p24 + a24 p44
+    q[9] += bb22; q[11] += a24 * bb22;
+    q[10] += bb23; q[13] += a24 * bb23;
+    q[11] += bb24; q[14] += a24 * bb24;
+    // b33 = a33 p33; b34 = a33 p34; b44 = a44 p44
+    q[12] += a33 * bb33;
+    q[13] += a33 * bb34;
+    q[14] += a44 * bb44;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) pb[i] = q[i];
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// Largest eigenvalue of [[a, b], [b, c]] and its partial derivatives (the
+// root's derivative taken as 0 where the root is 0).
+__device__ __forceinline__ float lmax_grad(float a, float b, float c, float &da, float &db, float &dc) {
+    const float h = 0.5f * (a - c);
+    const float s = sqrtf(h * h + b * b);
+    if (s > 0.0f) {
+        da = 0.5f + 0.5f * h / s;
+        dc = 0.5f - 0.5f * h / s;
+        db = b / s;
+    } else {
+        da = 0.5f;
+        dc = 0.5f;
+        db = 0.0f;
+    }
+    return 0.5f * (a + c) + s;
+}
+
+}  // namespace
+
+
+namespace {
+
+// Dynamic LDS: [k operand 32 x Mpad FP32][staged inputs][r: 32 x (Mpad + 1) FP32]
+__host__ __device__ constexpr size_t grad_rbuf_off(int Mpad) {
+    return kgroup_bytes<GPMPPI_FP32>(Mpad) + (size_t)staged_slots<GPMPPI_FP32>(Mpad) * 16;
+}
+__host__ __device__ constexpr size_t grad_lds_bytes(int Mpad) {
+    return grad_rbuf_off(Mpad) + (size_t)kB * (Mpad + 1) * 4;
+}
+
+__device__ __forceinline__ void restage(const GpDev &g, int o, unsigned char *lds) {
+    __syncthreads();
+    StagedInputs st;
+    stage_load<GPMPPI_FP32>(st, g, o);
+    stage_store<GPMPPI_FP32>(st, g, lds, kgroup_bytes<GPMPPI_FP32>(g.Mpad));
+    __syncthreads();
+}
+
+// FP32 kernel vector of output o for this thread's sample into the k operand.
+__device__ __forceinline__ void gen_kvec(const GpDev &g, int o, const float qs[4], int part, int sl,
+                                         unsigned char *lds) {
+    const int Mpad = g.Mpad, nchunk = Mpad >> 3;
+    const float4 *zs = reinterpret_cast<const float4 *>(lds + kgroup_bytes<GPMPPI_FP32>(Mpad));
+    const float c2 = g.c2[o];
+    for (int c = part; c < nchunk; c += kParts) {
+        float kv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float4 z = zs[8 * c + e];
+            const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
+            float acc = c2;
+            acc = fmaf(-d0, d0, acc);
+            acc = fmaf(-d1, d1, acc);
+            acc = fmaf(-d2, d2, acc);
+            acc = fmaf(-d3, d3, acc);
+            kv[e] = __builtin_amdgcn_exp2f(acc);
+        }
+        float4 *Kp = reinterpret_cast<float4 *>(lds) + (size_t)c * 64;
+        Kp[sl] = make_float4(kv[0], kv[2], kv[4], kv[6]);
+        Kp[32 + sl] = make_float4(kv[1], kv[3], kv[5], kv[7]);
+    }
+}
+
+// r = Q k for the block's 32 samples: wave w computes row tiles t = w, w+4, ...
+// over all column tiles, writing r[s][j] (row stride Mpad + 1) to LDS.
+__device__ __forceinline__ void qk_walk(const GradArgs &a, int o, unsigned char *lds) {
+    const int Mpad = a.gp.Mpad, NT = Mpad >> 5;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float4 *Qo = a.q32 + (size_t)o * a.q_stride;
+    float *rb = reinterpret_cast<float *>(lds + grad_rbuf_off(Mpad));
+    for (int t = w; t < NT; t += kWaves) {
+        v16f acc = v16f{};
+        WBlock<GPMPPI_FP32> cur, nxt;
+        {
+            const float4 *p = Qo + (size_t)(t * NT) * 256 + lane;
+            cur.v[0] = p[0];
+            cur.v[1] = p[64];
+            cur.v[2] = p[128];
+            cur.v[3] = p[192];
+        }
+        for (int it = 0; it < NT; ++it) {
+            if (it + 1 < NT) {
+                const float4 *p = Qo + (size_t)(t * NT + it + 1) * 256 + lane;
+                nxt.v[0] = p[0];
+                nxt.v[1] = p[64];
+                nxt.v[2] = p[128];
+                nxt.v[3] = p[192];
+            }
+            KOp<GPMPPI_FP32> kop;
+            load_kop<GPMPPI_FP32>(kop, lds, it, lane, Mpad);
+            mma_block<GPMPPI_FP32>(acc, cur, kop);
+            cur = nxt;
+        }
+        const int s = lane & 31;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = 32 * t + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            rb[s * (Mpad + 1) + row] = acc[e];
+        }
+    }
+}
+
+// Argmin over this part's polyline segments and obstacles, reduced over the
+// parts through LDS (smallest value, then smallest index).
+__device__ __forceinline__ void constraint_scan(const Geometry &geo, float X, float Y, float sa, float sb, float sc,
+                                                float lmax, int part, int sl, float *vb, int *ib, float *vo, int *io,
+                                                float &best_all, int &iseg, float &om_all, int &iobs) {
+    float best = INFINITY, om = INFINITY;
+    int bi = -1, oi = -1;
+    if (geo.path_kind != 0) {
+        for (int i = part; i < geo.P; i += kParts) {
+            const float4 sgm = geo.seg[i];
+            const float rx = X - sgm.x, ry = Y - sgm.y;
+            float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
+            t = fminf(fmaxf(t, 0.0f), 1.0f);
+            const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
+            const float d2 = ex * ex + ey * ey;
+            if (d2 < best) {
+                best = d2;
+                bi = i;
+            }
+        }
+    }
+    for (int j = part; j < geo.n_obs; j += kParts) {
+        const float4 ob = geo.obs[j];
+        const float dx = X - ob.x, dyy = Y - ob.y;
+        const float rho2 = dx * dx + dyy * dyy;
+        const float rho = sqrtf(rho2);
+        const float vn = rho > 0.0f ? (sa * dx * dx + 2.0f * sb * dx * dyy + sc * dyy * dyy) / rho2 : lmax;
+        const float m = (rho - ob.z) - geo.z_p * sqrtf(fmaxf(vn, 0.0f));
+        if (m < om) {
+            om = m;
+            oi = j;
+        }
+    }
+    __syncthreads();
+    vb[part * kB + sl] = best;
+    ib[part * kB + sl] = bi;
+    vo[part * kB + sl] = om;
+    io[part * kB + sl] = oi;
+    __syncthreads();
+    best_all = INFINITY;
+    om_all = INFINITY;
+    iseg = -1;
+    iobs = -1;
+#pragma unroll
+    for (int p = 0; p < kParts; ++p) {
+        const float b = vb[p * kB + sl], m = vo[p * kB + sl];
+        const int bx = ib[p * kB + sl], mx = io[p * kB + sl];
+        if (b < best_all || (b == best_all && bx >= 0 && (iseg < 0 || bx < iseg))) {
+            best_all = b;
+            iseg = bx;
+        }
+        if (m < om_all || (m == om_all && mx >= 0 && (iobs < 0 || mx < iobs))) {
+            om_all = m;
+            iobs = mx;
+        }
+    }
+}
+
+// Lane distance and its gradient in (X, Y).
+__device__ __forceinline__ float lane_dist_grad(const Geometry &geo, float X, float Y, float best_all, int iseg,
+                                                float &gx, float &gy) {
+    gx = 0.0f;
+    gy = 0.0f;
+    if (geo.path_kind == 0) {
+        const float dx = X - geo.cx, dyy = Y - geo.cy;
+        const float rho = sqrtf(dx * dx + dyy * dyy);
+        const float d = rho - geo.R;
+        if (rho > 0.0f && d != 0.0f) {
+            const float sg = d > 0.0f ? 1.0f : -1.0f;
+            gx = sg * dx / rho;
+            gy = sg * dyy / rho;
+        }
+        return fabsf(d);
+    }
+    const float dl = sqrtf(best_all);
+    if (iseg >= 0 && dl > 0.0f) {
+        const float4 sgm = geo.seg[iseg];
+        const float rx = X - sgm.x, ry = Y - sgm.y;
+        float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[iseg];
+        t = fminf(fmaxf(t, 0.0f), 1.0f);
+        gx = (rx - t * sgm.z) / dl;
+        gy = (ry - t * sgm.w) / dl;
+    }
+    return dl;
+}
+
+__device__ __forceinline__ void seg_put(float *base, int f, float v) { base[f * kB] = v; }
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ float pred[kParts * kB];
+    __shared__ float vred[kWaves * kB];
+    __shared__ float vb[kParts * kB], vo[kParts * kB];
+    __shared__ int ib[kParts * kB], io[kParts * kB];
+    __shared__ float gred[9 * kParts * kB];
+    __shared__ float mb_s[2][kB], sb_s[2][kB], ub_s[2][kB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int sl = lane & 31;
+    const int part = 2 * w + (lane >> 5);
+    const int blk = blockIdx.x;
+    const int sg = blk * kB + sl;
+    const bool valid = sg < a.K;
+    const bool writer = w == 0 && lane < kB;   // one copy of each sample
+    const int K = a.K, T = a.T, C = a.C;
+    const int Mpad = a.gp.Mpad;
+    const GpDev &g = a.gp;
+    const Geometry &geo = a.geo;
+    const CostWeights cw = a.cw;
+    const Dyn dy = a.dyn;
+    const float dt = dy.dt;
+    const float cbar = valid ? a.inv_K : 0.0f;
+    float *segw = a.seg + (size_t)blk * (C + 1) * kSegF * kB + sl;   // [e][f][32]
+    float *rb = reinterpret_cast<float *>(lds + grad_rbuf_off(Mpad));
+
+    NoiseParams np = a.noise;
+
+    // per-sample accumulators of the hyperparameter terms through k (o, theta)
+    float hyp[2][5] = {};
+    // this thread's share of b = sum mbar r (points j = tid + 256 i)
+    float bacc[2][2] = {};
+
+    const int nseg = (T + C - 1) / C;
+    float X = 0, Y = 0, th = 0, v = 0, w_ = 0;
+    float p[15];
+    // adjoint of the state after the step being reversed, carried between segments
+    float xb[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float pb[15] = {};
+    float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
+
+    for (int job = 0; job <= nseg; ++job) {
+        const bool first = job == 0;
+        const int segi = first ? 0 : nseg - job;
+        const int k0 = first ? 0 : segi * C;
+        const int k1 = first ? T : min(T, k0 + C);
+        if (first) {
+            X = a.x0[0]; Y = a.x0[1]; th = a.x0[2]; v = a.x0[3]; w_ = a.x0[4];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) p[i] = 0.0f;
+        } else {
+            const float *ck = a.ckpt + (size_t)segi * kCkF * K + (valid ? sg : 0);
+            X = ck[0 * (size_t)K]; Y = ck[1 * (size_t)K]; th = ck[2 * (size_t)K]; v = ck[3 * (size_t)K];
+            w_ = ck[4 * (size_t)K];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) p[i] = ck[(5 + i) * (size_t)K];
+        }
+        restage(g, (k0 & 1) ? 1 : 0, lds);
+        // ---------------------------------------------------------- forward
+        for (int k = k0; k < k1; ++k) {
+            if (writer) {
+                if (first && k % C == 0 && valid) {
+                    float *ck = a.ckpt + (size_t)(k / C) * kCkF * K + sg;
+                    ck[0 * (size_t)K] = X; ck[1 * (size_t)K] = Y; ck[2 * (size_t)K] = th; ck[3 * (size_t)K] = v;
+                    ck[4 * (size_t)K] = w_;
+#pragma unroll
+                    for (int i = 0; i < 15; ++i) ck[(5 + i) * (size_t)K] = p[i];
+                }
+                if (!first) {
+                    float *e = segw + (size_t)(k - k0) * kSegF * kB;
+                    seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
+#pragma unroll
+                    for (int i = 0; i < 15; ++i) seg_put(e, 5 + i, p[i]);
+                }
+            }
+            const bool rev = (k & 1) != 0;
+            const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
+            const float q[4] = {v, w_, u.x, u.y};
+            float m[2], s2[2];
+#pragma unroll
+            for (int oo = 0; oo < 2; ++oo) {
+                const int o = rev ? 1 - oo : oo;
+                __syncthreads();
+                const float qs[4] = {q[0] * g.scale[o][0], q[1] * g.scale[o][1], q[2] * g.scale[o][2],
+                                     q[3] * g.scale[o][3]};
+                gp_output<GPMPPI_FP32, 1>(g, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, 0, blk, lds, pred, vred,
+                                          m[o], s2[o]);
+            }
+            float sth, cth;
+            sincosf(th, &sth, &cth);
+            const Jac J{-dt * v * sth, dt * cth, dt * v * cth, dt * sth};
+            const float Xn = X + dt * v * cth;
+            const float Yn = Y + dt * v * sth;
+            const float thn = th + dt * w_;
+            const float vn = v + (dy.dt_tau_v * (u.x - v) + dt * m[0]);
+            const float wn = w_ + (dy.dt_tau_w * (u.y - w_) + dt * m[1]);
+            float P[15];
+            cov_forward(p, J, dt, dy.a33, dy.a44, dt * dt * s2[0], dt * dt * s2[1], P);
+#pragma unroll
+            for (int i = 0; i < 15; ++i) p[i] = P[i];
+            X = Xn; Y = Yn; th = thn; v = vn; w_ = wn;
+            if (!first && writer) {
+                float *e = segw + (size_t)(k - k0) * kSegF * kB;
+                seg_put(e, 20, u.x); seg_put(e, 21, u.y); seg_put(e, 22, m[0]); seg_put(e, 23, m[1]);
+                seg_put(e, 24, s2[0]); seg_put(e, 25, s2[1]);
+                seg_put(e, 26, s2[0] > g.sn2[0] ? 1.0f : 0.0f);
+                seg_put(e, 27, s2[1] > g.sn2[1] ? 1.0f : 0.0f);
+            }
+            if (first) {
+                // smoothed stage cost on (x_{k+1}, Sigma_{k+1})
+                const float sa = p[0], sb = p[1], sc = p[5];
+                float da, db, dc;
+                const float lmax = lmax_grad(sa, sb, sc, da, db, dc);
+                float best_all, om_all;
+                int iseg, iobs;
+                constraint_scan(geo, X, Y, sa, sb, sc, lmax, part, sl, vb, ib, vo, io, best_all, iseg, om_all,
+                                iobs);
+                float gx, gy;
+                const float dl = lane_dist_grad(geo, X, Y, best_all, iseg, gx, gy);
+                const float rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
+                const float dv = cw.v_des - v;
+                float c = cw.w_var * (s2[0] + s2[1]) + cw.w_dev * (dl * geo.inv_half_width) + cw.w_speed * (dv * dv);
+                c += cw.w_lane * disc * sigmoidf((dl - rbar) * a.inv_tau);
+                if (geo.n_obs > 0) c += cw.w_obs * sigmoidf(-om_all * a.inv_tau);
+                const float yk = c - Sc;
+                const float tk = S_ + yk;
+                Sc = (tk - S_) - yk;
+                S_ = tk;
+                disc *= cw.discount;
+            }
+        }
+        if (first) {
+            if (writer && valid) a.costs[sg] = S_;
+            continue;
+        }
+        if (writer) {   // the segment's final state
+            float *e = segw + (size_t)(k1 - k0) * kSegF * kB;
+            seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
+#pragma unroll
+            for (int i = 0; i < 15; ++i) seg_put(e, 5 + i, p[i]);
+        }
+        __syncthreads();   // segment scratch visible to every copy of each sample
+
+        // ---------------------------------------------------------- backward
+        for (int k = k1 - 1; k >= k0; --k) {
+            const float *e1 = segw + (size_t)(k + 1 - k0) * kSegF * kB;   // x_{k+1}, p_{k+1}
+            const float *e0 = segw + (size_t)(k - k0) * kSegF * kB;       // x_k, p_k, u, m, s2, flags
+            const float X1 = e1[0], Y1 = e1[kB], v1 = e1[3 * kB];
+            const float sa = e1[(5 + 0) * kB], sb = e1[(5 + 1) * kB], sc = e1[(5 + 5) * kB];
+            const float thk = e0[2 * kB], vk = e0[3 * kB], wk = e0[4 * kB];
+            float pk[15];
+#pragma unroll
+            for (int i = 0; i < 15; ++i) pk[i] = e0[(5 + i) * kB];
+            const float ux = e0[20 * kB], uy = e0[21 * kB];
+            const float flag[2] = {e0[26 * kB], e0[27 * kB]};
+
+            // ---- stage cost adjoint at (x_{k+1}, Sigma_{k+1}, s2_k)
+            float da, db, dc;
+            const float lmax = lmax_grad(sa, sb, sc, da, db, dc);
+            float best_all, om_all;
+            int iseg, iobs;
+            constraint_scan(geo, X1, Y1, sa, sb, sc, lmax, part, sl, vb, ib, vo, io, best_all, iseg, om_all, iobs);
+            float gx, gy;
+            const float dl = lane_dist_grad(geo, X1, Y1, best_all, iseg, gx, gy);
+            const float sq = sqrtf(fmaxf(lmax, 0.0f));
+            const float rbar = geo.half_width - geo.c_p * sq;
+            float discount_k = 1.0f;
+            for (int i = 0; i < k; ++i) discount_k *= cw.discount;
+            float s2b[2] = {cbar * cw.w_var, cbar * cw.w_var};
+            float lamb = 0.0f;   // adjoint of lambda_max(Sigma_XY)
+            float dlb = cbar * cw.w_dev * geo.inv_half_width;
+            {
+                const float sL = sigmoidf((dl - rbar) * a.inv_tau);
+                const float gL = cbar * cw.w_lane * discount_k * sL * (1.0f - sL) * a.inv_tau;
+                dlb += gL;
+                if (sq > 0.0f) lamb += -gL * (-geo.c_p) * 0.5f / sq;
+            }
+            float Xb1 = gx * dlb, Yb1 = gy * dlb;
+            float Sab = 0.0f, Sbb = 0.0f, Scb = 0.0f;
+            if (geo.n_obs > 0 && iobs >= 0) {
+                const float sO = sigmoidf(-om_all * a.inv_tau);
+                const float omb = -cbar * cw.w_obs * sO * (1.0f - sO) * a.inv_tau;
+                const float4 ob = geo.obs[iobs];
+                const float dx = X1 - ob.x, dyy = Y1 - ob.y;
+                const float rho2 = dx * dx + dyy * dyy;
+                const float rho = sqrtf(rho2);
+                float var;
+                if (rho > 0.0f) {
+                    var = (sa * dx * dx + 2.0f * sb * dx * dyy + sc * dyy * dyy) / rho2;
+                    Xb1 += omb * dx / rho;
+                    Yb1 += omb * dyy / rho;
+                } else {
+                    var = lmax;
+                }
+                const float sv = sqrtf(fmaxf(var, 0.0f));
+                const float varb = sv > 0.0f ? omb * (-geo.z_p) * 0.5f / sv : 0.0f;
+                if (rho > 0.0f) {
+                    Xb1 += varb * 2.0f * (sa * dx + sb * dyy - var * dx) / rho2;
+                    Yb1 += varb * 2.0f * (sb * dx + sc * dyy - var * dyy) / rho2;
+                    Sab += varb * dx * dx / rho2;
+                    Sbb += varb * 2.0f * dx * dyy / rho2;
+                    Scb += varb * dyy * dyy / rho2;
+                } else {
+                    lamb += varb;
+                }
+            }
+            Sab += lamb * da;
+            Sbb += lamb * db;
+            Scb += lamb * dc;
+            // adjoint of x_{k+1}, Sigma_{k+1}: carried part plus this stage's
+            const float Xn_b = xb[0] + Xb1, Yn_b = xb[1] + Yb1, thn_b = xb[2];
+            const float vn_b = xb[3] + cbar * cw.w_speed * (-2.0f) * (cw.v_des - v1), wn_b = xb[4];
+            pb[0] += Sab;
+            pb[1] += Sbb;
+            pb[5] += Scb;
+
+            // ---- covariance adjoint
+            float sth, cth;
+            sincosf(thk, &sth, &cth);
+            const Jac Jk{-dt * vk * sth, dt * cth, dt * vk * cth, dt * sth};
+            Jac Jb{0.0f, 0.0f, 0.0f, 0.0f};
+            float e3b, e4b, pbk[15];
+            cov_backward(pk, Jk, dt, dy.a33, dy.a44, pb, pbk, Jb, e3b, e4b);
+            s2b[0] += dt * dt * e3b;
+            s2b[1] += dt * dt * e4b;
+
+            // ---- Euler step adjoint (x_{k+1} = f(x_k, u, m)) and the Jacobian's
+            float thb = -Xn_b * dt * vk * sth + Yn_b * dt * vk * cth + thn_b;
+            float vbk = Xn_b * dt * cth + Yn_b * dt * sth + vn_b * (1.0f - dy.dt_tau_v);
+            float wbk = thn_b * dt + wn_b * (1.0f - dy.dt_tau_w);
+            float uxb = vn_b * dy.dt_tau_v, uyb = wn_b * dy.dt_tau_w;
+            const float mb[2] = {vn_b * dt, wn_b * dt};
+            thb += Jb.a02 * (-dt * vk * cth) + Jb.a03 * (-dt * sth) + Jb.a12 * (-dt * vk * sth) + Jb.a13 * (dt * cth);
+            vbk += Jb.a02 * (-dt * sth) + Jb.a12 * (dt * cth);
+
+            // ---- GP adjoint, both outputs
+            const float qk[4] = {vk, wk, ux, uy};
+            float qb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int o = 0; o < 2; ++o) {
+                const float sbo = s2b[o] * flag[o];
+                if (writer) {
+                    mb_s[o][sl] = mb[o];
+                    sb_s[o][sl] = sbo;
+                }
+                restage(g, o, lds);   // also publishes mb_s / sb_s
+                const float qs[4] = {qk[0] * g.scale[o][0], qk[1] * g.scale[o][1], qk[2] * g.scale[o][2],
+                                     qk[3] * g.scale[o][3]};
+                gen_kvec(g, o, qs, part, sl, lds);
+                __syncthreads();
+                qk_walk(a, o, lds);
+                __syncthreads();
+                // per-sample sums over this part's points
+                const float4 *zs = reinterpret_cast<const float4 *>(lds + kgroup_bytes<GPMPPI_FP32>(Mpad));
+                const float *al = reinterpret_cast<const float *>(zs + Mpad);
+                float Sb = 0.0f, Sd[4] = {0, 0, 0, 0}, Sdd[4] = {0, 0, 0, 0};
+                for (int c = part; c < (Mpad >> 3); c += kParts) {
+                    const float4 *Kp = reinterpret_cast<const float4 *>(lds) + (size_t)c * 64;
+                    const float4 lo = Kp[sl], hi = Kp[32 + sl];
+                    const float kv[8] = {lo.x, hi.x, lo.y, hi.y, lo.z, hi.z, lo.w, hi.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int j = 8 * c + e;
+                        const float4 z = zs[j];
+                        const float beta = kv[e] * (2.0f * sbo * rb[sl * (Mpad + 1) + j] - mb[o] * al[j]);
+                        const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
+                        Sb += beta;
+                        Sd[0] = fmaf(beta, d0, Sd[0]);
+                        Sd[1] = fmaf(beta, d1, Sd[1]);
+                        Sd[2] = fmaf(beta, d2, Sd[2]);
+                        Sd[3] = fmaf(beta, d3, Sd[3]);
+                        Sdd[0] = fmaf(beta * d0, d0, Sdd[0]);
+                        Sdd[1] = fmaf(beta * d1, d1, Sdd[1]);
+                        Sdd[2] = fmaf(beta * d2, d2, Sdd[2]);
+                        Sdd[3] = fmaf(beta * d3, d3, Sdd[3]);
+                    }
+                }
+                gred[(0 * kParts + part) * kB + sl] = Sb;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    gred[((1 + d) * kParts + part) * kB + sl] = Sd[d];
+                    gred[((5 + d) * kParts + part) * kB + sl] = Sdd[d];
+                }
+                // b += sum_s mbar_s r_s over this thread's points; the r rows for P
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int j = tid + kThreads * jj;
+                    if (j < Mpad) {
+                        float acc = bacc[o][jj];
+                        float *Rrow = a.R + ((size_t)o * T * K + (size_t)k * K + (size_t)blk * kB) * Mpad + j;
+                        for (int s = 0; s < kB; ++s) {
+                            if (blk * kB + s < K) {
+                                const float rv = rb[s * (Mpad + 1) + j];
+                                acc = fmaf(mb_s[o][s], rv, acc);
+                                Rrow[(size_t)s * Mpad] = rv;
+                            }
+                        }
+                        bacc[o][jj] = acc;
+                    }
+                }
+                if (writer && valid) a.Gw[(size_t)o * T * K + (size_t)k * K + sg] = sbo;
+                __syncthreads();
+                float tot[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int pp = 0; pp < kParts; ++pp) sum += gred[(i * kParts + pp) * kB + sl];
+                    tot[i] = sum;
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    qb[d] += 2.0f * kLn2 * g.scale[o][d] * tot[1 + d];
+                    hyp[o][d] += -2.0f * kLn2 * tot[5 + d];
+                }
+                hyp[o][4] += -2.0f * tot[0] + 2.0f * g.sf2[o] * sbo;
+            }
+            vbk += qb[0];
+            wbk += qb[1];
+            uxb += qb[2];
+            uyb += qb[3];
+
+            // ---- the nominal control's adjoint through the clip (1 strictly inside the box)
+            {
+                const float2 raw = sampled_raw(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
+                const float m0 = (raw.x > np.umin0 && raw.x < np.umax0) ? 1.0f : 0.0f;
+                const float m1 = (raw.y > np.umin1 && raw.y < np.umax1) ? 1.0f : 0.0f;
+                if (writer) {
+                    ub_s[0][sl] = valid ? uxb * m0 : 0.0f;
+                    ub_s[1][sl] = valid ? uyb * m1 : 0.0f;
+                }
+                __syncthreads();
+                if (tid < 2) {
+                    float sum = 0.0f;
+                    for (int i = 0; i < kB; ++i) sum += ub_s[tid][i];
+                    a.upart[((size_t)blk * T + k) * 2 + tid] = sum;
+                }
+            }
+            xb[0] = Xn_b;
+            xb[1] = Yn_b;
+            xb[2] = thb;
+            xb[3] = vbk;
+            xb[4] = wbk;
+#pragma unroll
+            for (int i = 0; i < 15; ++i) pb[i] = pbk[i];
+        }
+    }
+    (void)np;
+    // ---- per-workgroup partial sums
+    __syncthreads();
+    if (writer) {
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) gred[(o * 5 + i) * kB + sl] = valid ? hyp[o][i] : 0.0f;
+    }
+    __syncthreads();
+    if (tid < 10) {
+        float s = 0.0f;
+        for (int i = 0; i < kB; ++i) s += gred[tid * kB + i];
+        a.hpart[(size_t)blk * 10 + tid] = s;
+    }
+    for (int o = 0; o < 2; ++o)
+        for (int jj = 0; jj < 2; ++jj) {
+            const int j = tid + kThreads * jj;
+            if (j < Mpad) a.bpart[((size_t)blk * 2 + o) * Mpad + j] = bacc[o][jj];
+        }
+}
+
+
+// dA_ij / dtheta contracted with a weight c_ij, theta = (log ell_0..3, log sf):
+// K_ij = exp2(c2 - |zs_i - zs_j|^2); dA/dlog ell_d = K 2 ln2 (zs_id - zs_jd)^2,
+// dA/dlog sf = 2 K (the sn^2 I part does not depend on them).
+__device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const float4 &zj, float c2, float acc[5]) {
+    const float d0 = zi.x - zj.x, d1 = zi.y - zj.y, d2 = zi.z - zj.z, d3 = zi.w - zj.w;
+    const float e0 = d0 * d0, e1 = d1 * d1, e2 = d2 * d2, e3 = d3 * d3;
+    const float Kij = __builtin_amdgcn_exp2f(c2 - (e0 + e1 + e2 + e3));
+    const float ck = cval * Kij;
+    const float c2l = 2.0f * kLn2 * ck;
+    acc[0] = fmaf(c2l, e0, acc[0]);
+    acc[1] = fmaf(c2l, e1, acc[1]);
+    acc[2] = fmaf(c2l, e2, acc[2]);
+    acc[3] = fmaf(c2l, e3, acc[3]);
+    acc[4] = fmaf(2.0f, ck, acc[4]);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += shfl_xor(x, m);
+    return x;
+}
+
+// P = sum_n g_n r_n r_n^T over rows n in [n0, n1) of one output, for one
+// 128 x 128 block (bi <= bj) of the Mpad x Mpad result, contracted with dA/dtheta:
+// ppart[((o * npairs + pair) * nsplit + split) * 5 + theta].  Wave w owns the
+// 32 x 32 tiles (2 (w >> 1) + {0, 1}, 2 (w & 1) + {0, 1}) of the block.
+__global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, const float *Gw, long long TK, int Mpad,
+                                                             const float *zs, float c20, float c21, int nsplit,
+                                                             float *ppart) {
+    __shared__ float red[kWaves][5];
+    const int pair = blockIdx.x, split = blockIdx.y, o = blockIdx.z;
+    const int npairs = gridDim.x;
+    const int nb = (Mpad + 127) / 128;
+    int bi = 0, rem = pair;
+    while (rem >= nb - bi) {
+        rem -= nb - bi;
+        ++bi;
+    }
+    const int bj = bi + rem;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ti0 = 4 * bi + 2 * (w >> 1), tj0 = 4 * bj + 2 * (w & 1);
+    const int NT = Mpad >> 5;
+    const bool vi[2] = {ti0 < NT, ti0 + 1 < NT}, vj[2] = {tj0 < NT, tj0 + 1 < NT};
+    const long long chunk = (TK + nsplit - 1) / nsplit;
+    const long long n0 = (long long)split * chunk;
+    const long long n1 = n0 + chunk < TK ? n0 + chunk : TK;
+    const float *Ro = R + (size_t)o * TK * Mpad;
+    const float *Go = Gw + (size_t)o * TK;
+    v16f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v16f{};
+    const int col = lane & 31, rsel = lane >> 5;
+    for (long long n = n0; n < n1; n += 2) {
+        const long long row = n + rsel;
+        const bool ok = row < n1;
+        const float gv = ok ? Go[row] : 0.0f;
+        const float *rp = Ro + (size_t)(ok ? row : n0) * Mpad;
+        float av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = (vi[i] && ok) ? gv * rp[32 * (ti0 + i) + col] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = (vj[j] && ok) ? rp[32 * (tj0 + j) + col] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    // epilogue: sum_ij P_ij dA_ij/dtheta over the wave's tiles (both triangles of a
+    // diagonal block; off-diagonal blocks stand for their mirror image too)
+    const float c2 = o ? c21 : c20;
+    const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
+    const float weight = bi == bj ? 1.0f : 2.0f;
+    float cacc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!vi[i] || !vj[j]) continue;
+            const float4 zj = z[32 * (tj0 + j) + col];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = 32 * (ti0 + i) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                dA_contract(weight * acc[i][j][e], z[row], zj, c2, cacc);
+            }
+        }
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        const float v = wave_sum(cacc[t]);
+        if (lane == 0) red[w][t] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        ppart[((size_t)(o * npairs + pair) * nsplit + split) * 5 + threadIdx.x] = v;
+    }
+}
+
+// b = sum over workgroups of the partial b, then sum_ij b_i alpha_j dA_ij/dtheta:
+// one thread per row i; bterm[(o * gridDim.x + block) * 5 + theta].
+__global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const float *bpart, int nwg, int Mpad, const float *zs,
+                                                              const float *alpha, float c20, float c21,
+                                                              float *bterm) {
+    __shared__ float red[kWaves][5];
+    const int o = blockIdx.y;
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const float c2 = o ? c21 : c20;
+    const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
+    const float *al = alpha + (size_t)o * Mpad;
+    float cacc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (i < Mpad) {
+        float b = 0.0f;
+        for (int wg = 0; wg < nwg; ++wg) b += bpart[((size_t)wg * 2 + o) * Mpad + i];
+        const float4 zi = z[i];
+        for (int j = 0; j < Mpad; ++j) dA_contract(b * al[j], zi, z[j], c2, cacc);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        const float v = wave_sum(cacc[t]);
+        if (lane == 0) red[w][t] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        bterm[((size_t)o * gridDim.x + blockIdx.x) * 5 + threadIdx.x] = v;
+    }
+}
+
+// Fixed-order final sums: J = mean smoothed cost, dU[k][c], and the
+// hyperparameter gradient = direct (through k) + (P - b alpha^T) : dA/dtheta.
+__global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs, int K, int T, int nwg,
+                                                              const float *upart, const float *hpart,
+                                                              const float *ppart, int nppart, const float *bterm,
+                                                              int nbterm, float *J, float *dU, float *dlog_ell,
+                                                              float *dlog_sf) {
+    __shared__ float red[kThreads];
+    const int tid = threadIdx.x;
+    float s = 0.0f;
+    for (int i = tid; i < K; i += kThreads) s += costs[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) J[0] = red[0] / (float)K;
+    for (int kc = tid; kc < 2 * T; kc += kThreads) {
+        float v = 0.0f;
+        for (int wg = 0; wg < nwg; ++wg) v += upart[(size_t)wg * 2 * T + kc];
+        dU[kc] = v;
+    }
+    if (tid < 10) {
+        const int o = tid / 5, t = tid % 5;
+        float direct = 0.0f, mat = 0.0f, bt = 0.0f;
+        for (int wg = 0; wg < nwg; ++wg) direct += hpart[(size_t)wg * 10 + tid];
+        for (int i = 0; i < nppart; ++i) mat += ppart[((size_t)o * nppart + i) * 5 + t];
+        for (int i = 0; i < nbterm; ++i) bt += bterm[((size_t)o * nbterm + i) * 5 + t];
+        const float g = direct + mat - bt;
+        if (t < 4) dlog_ell[o * 4 + t] = g;
+        else dlog_sf[o] = g;
+    }
+}
+
+size_t grad_lds(int Mpad) { return grad_lds_bytes(Mpad); }
+
+hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st) {
+    const size_t lds = grad_lds_bytes(a.gp.Mpad);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_kernel, dim3(l.nwg), dim3(kThreads), lds, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const long long TK = (long long)a.T * a.K;
+    hipLaunchKernelGGL(grad_syrk_kernel, dim3(l.npairs, l.nsplit, 2), dim3(kThreads), 0, st, a.R, a.Gw, TK, a.gp.Mpad,
+                       a.gp.zs, a.gp.c2[0], a.gp.c2[1], l.nsplit, l.ppart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_bterm_kernel, dim3(l.nbterm, 2), dim3(kThreads), 0, st, a.bpart, l.nwg, a.gp.Mpad,
+                       a.gp.zs, a.gp.alpha, a.gp.c2[0], a.gp.c2[1], l.bterm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_final_kernel, dim3(1), dim3(kThreads), 0, st, a.costs, a.K, a.T, l.nwg, a.upart, a.hpart,
+                       l.ppart, l.npairs * l.nsplit, l.bterm, l.nbterm, l.J, l.dU, l.dlog_ell, l.dlog_sf);
+    return hipGetLastError();
+}
+
+}  // namespace gpmppi

@@ -144,6 +144,42 @@ hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, Terrain
                          float *alpha32, float *cza, hipStream_t st);
 hipError_t launch_terrain_means(const float *q, int n, const GpDev &g, const double *alpha_terr, int n_terr,
                                 float *out, hipStream_t st);
+// Differentiation form (the adjoint rollout and its reductions).
+struct GradArgs {
+    GpDev gp;
+    Geometry geo;
+    CostWeights cw;
+    Dyn dyn;
+    NoiseParams noise;
+    int K, T, C, nck;
+    float inv_tau, inv_K;
+    const float4 *q32;       // dense packed Q per output
+    long long q_stride;      // float4 per output
+    const float *x0;         // [5]
+    const float *U;          // [T][2]
+    float *costs;            // [K] smoothed costs
+    float *ckpt;             // [nck][20][K]
+    float *seg;              // [nwg][C + 1][28][32] per-workgroup segment scratch
+    float *R;                // [2][T K][Mpad]
+    float *Gw;               // [2][T K]
+    float *bpart;            // [nwg][2][Mpad]
+    float *hpart;            // [nwg][10]
+    float *upart;            // [nwg][T][2]
+};
+
+struct GradLaunch {
+    int nwg;                 // grad_kernel workgroups = ceil(K / 32)
+    int npairs, nsplit;      // grad_syrk_kernel grid: 128-blocks (bi <= bj) x row splits
+    int nbterm;              // grad_bterm_kernel blocks per output
+    float *ppart, *bterm;    // partial contractions
+    float *J, *dU, *dlog_ell, *dlog_sf;   // outputs
+};
+// Dynamic LDS of grad_kernel at this Mpad (must be <= 160 KB minus its static LDS).
+size_t grad_lds(int Mpad);
+hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st);
+
+// Q = A^-1 = W^T W packed dense (FP32 operand order); overwrites b.A.
+hipError_t pack_q(const GpBuildBuffers &b, int M, int Mpad, float4 *q32, hipStream_t st);
 hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st);
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
                           float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,

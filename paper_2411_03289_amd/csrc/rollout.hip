@@ -22,436 +22,9 @@
 //     small for both outputs' W still keeps most of it between steps.
 //  3. per-sample Euler step, covariance A Sigma A^T + dt^2 diag(0,0,0,s2),
 //     lane/obstacle tightening and the stage cost.
-#include "device_common.hpp"
-#include "kernels.hpp"
+#include "gp_tiles.hpp"
 
 namespace gpmppi {
-
-// ---------------------------------------------------------------- W blocks
-// W is walked in row-tile pairs (2u, 2u + 1), u < NP = NT / 2 (Mpad is a
-// multiple of 64, so NT = Mpad / 32 is even): pair u
-// takes 2u + 2 iterations it = 0 .. 2u + 1, each holding the two 32x32 blocks
-// (2u, it) and (2u + 1, it) of W (rows 32t.., columns 32 it..).  Block (2u, 2u+1)
-// lies above the diagonal and is stored as zeros, and so is every block of a
-// row tile beyond the matrix, so all iterations are alike.  Packed block index
-// b = 2 (u (u + 1) + it) + side, lane l of a wave:
-//   FP32: float4 [b][q][l], component c: W[32t + l%32][32 it + 2(4q+c) + l/32]
-//   BF16: uint4  [b][h][l], element e:   W[32t + l%32][32 it + 16h + 8(l/32) + e]
-// The LDS operand of sample group g holds k in the same lane order with the
-// sample 32g + l % 32 in place of the W row.
-template <int PREC>
-struct WBlock;
-template <>
-struct WBlock<GPMPPI_FP32> {
-    float4 v[4];
-};
-template <>
-struct WBlock<GPMPPI_BF16> {
-    uint4 h[2];
-};
-template <>
-struct WBlock<GPMPPI_BF16X3> {
-    uint4 h[2];
-    uint4 l[2];
-};
-
-// k operand of one sample group for one block column.
-template <int PREC>
-struct KOp;
-template <>
-struct KOp<GPMPPI_FP32> {
-    float4 v[4];
-};
-template <>
-struct KOp<GPMPPI_BF16> {
-    uint4 h[2];
-};
-template <>
-struct KOp<GPMPPI_BF16X3> {
-    uint4 h[2];
-    uint4 l[2];
-};
-
-template <int PREC>
-__device__ __forceinline__ void load_wblock(WBlock<PREC> &b, const GpDev &g, int o, int blk, int lane) {
-    if constexpr (PREC == GPMPPI_FP32) {
-        const float4 *p = g.w32 + o * g.w32_stride + (size_t)blk * 256 + lane;
-        b.v[0] = p[0];
-        b.v[1] = p[64];
-        b.v[2] = p[128];
-        b.v[3] = p[192];
-    } else {
-        const uint4 *p = g.wbh + o * g.wb_stride + (size_t)blk * 128 + lane;
-        b.h[0] = p[0];
-        b.h[1] = p[64];
-        if constexpr (PREC == GPMPPI_BF16X3) {
-            const uint4 *q = g.wbl + o * g.wb_stride + (size_t)blk * 128 + lane;
-            b.l[0] = q[0];
-            b.l[1] = q[64];
-        }
-    }
-}
-
-// Byte size of one sample group's k operand in LDS.
-template <int PREC>
-__host__ __device__ constexpr size_t kgroup_bytes(int Mpad) {
-    return (size_t)Mpad * 32 * (PREC == GPMPPI_BF16 ? 2 : 4);
-}
-
-template <int PREC>
-__device__ __forceinline__ void load_kop(KOp<PREC> &k, const unsigned char *kg, int jt, int lane, int Mpad) {
-    if constexpr (PREC == GPMPPI_FP32) {
-        const float4 *K = reinterpret_cast<const float4 *>(kg) + (size_t)jt * 256 + lane;
-        k.v[0] = K[0];
-        k.v[1] = K[64];
-        k.v[2] = K[128];
-        k.v[3] = K[192];
-    } else {
-        const uint4 *K = reinterpret_cast<const uint4 *>(kg) + (size_t)jt * 128 + lane;
-        k.h[0] = K[0];
-        k.h[1] = K[64];
-        if constexpr (PREC == GPMPPI_BF16X3) {
-            const uint4 *L = reinterpret_cast<const uint4 *>(kg + (size_t)Mpad * 64) + (size_t)jt * 128 + lane;
-            k.l[0] = L[0];
-            k.l[1] = L[64];
-        }
-    }
-}
-
-__device__ __forceinline__ v8bf as_bf(uint4 u) {
-    v8bf r;
-    __builtin_memcpy(&r, &u, 16);
-    return r;
-}
-
-template <int PREC>
-__device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, const KOp<PREC> &k) {
-    if constexpr (PREC == GPMPPI_FP32) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].x, k.v[q].x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].y, k.v[q].y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].z, k.v[q].z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].w, k.v[q].w, acc, 0, 0, 0);
-        }
-    } else {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(k.h[h]), acc, 0, 0, 0);
-            if constexpr (PREC == GPMPPI_BF16X3) {
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[h]), as_bf(k.l[h]), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[h]), as_bf(k.h[h]), acc, 0, 0, 0);
-            }
-        }
-    }
-}
-
-// Pair list of a wave: round i holds pairs 4i .. 4i+3, assigned in snake
-// order so that the summed pair lengths (2u + 2) balance across waves.
-__device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? 4 * i + 3 - w : 4 * i + w; }
-
-// Position in a wave's iteration sequence: n pairs visited so far, list
-// index i = (r0 + n) mod npairs (forward) or (r0 - 1 - n) mod npairs
-// (reverse), pair u and iteration it.  Forward: pairs in list order from r0,
-// it ascending; reverse: the exact reverse of that sequence.  Every pair has
-// an even length.
-struct Cursor {
-    int n, i, u, it;
-};
-
-__device__ __forceinline__ void cursor_set(Cursor &c, int w, int npairs, int r0, bool rev) {
-    int i = rev ? r0 - 1 - c.n : r0 + c.n;
-    i %= npairs;
-    if (i < 0) i += npairs;
-    c.i = i;
-    c.u = wave_pair(w, i);
-    c.it = rev ? 2 * c.u + 1 : 0;
-}
-
-__device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, int r0, bool rev) {
-    c.n = 0;
-    cursor_set(c, w, npairs, r0, rev);
-}
-
-// Advances; returns true when the iteration just left closed its pair.
-__device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0, bool rev) {
-    if (!rev) {
-        if (++c.it <= 2 * c.u + 1) return false;
-    } else {
-        if (--c.it >= 0) return false;
-    }
-    ++c.n;
-    cursor_set(c, w, npairs, r0, rev);
-    return true;
-}
-
-__device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (c.u + 1) + c.it); }
-
-
-template <int PREC>
-__host__ __device__ constexpr int staged_slots(int Mpad);
-
-template <int PREC, int G>
-struct Shapes {
-    static constexpr int B = 32 * G;                 // samples per block
-    static constexpr int parts = kWaves * (2 / G);   // loop splitters: waves (x half-waves for G = 1)
-};
-
-// Dynamic LDS layout: [G k-operand groups][zs: Mpad float4][alpha: Mpad float]
-template <int PREC, int G>
-__host__ __device__ constexpr size_t dyn_lds_bytes(int Mpad) {
-    return G * kgroup_bytes<PREC>(Mpad) + (size_t)staged_slots<PREC>(Mpad) * 16;
-}
-
-// One GP output for the B samples of the block; called by all threads.
-// Returns the sample's GP mean and predictive variance.
-// Per-point inputs of output o staged in LDS (float4 slots):
-//   FP32:        zs [Mpad] then alpha [Mpad / 4]            (20 B per point)
-//   BF16 forms:  2 zs [Mpad] then (c2 - |zs|^2, alpha) [Mpad / 2]  (24 B per point)
-// held in registers between their global load and their store to LDS; thread
-// t owns slots t, t + 256, ... (at most 1536 slots for Mpad <= 1024).
-template <int PREC>
-__host__ __device__ constexpr int staged_slots(int Mpad) {
-    return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : Mpad + (Mpad >> 1);
-}
-
-// Native vectors (not HIP's float4 struct, whose copies become memcpy of a
-// private array that the compiler keeps in scratch memory).
-struct StagedInputs {
-    v4f v[6];
-};
-
-template <int PREC>
-__device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
-    const int Mpad = g.Mpad, nz = Mpad, ns = staged_slots<PREC>(Mpad);
-    const v4f *zsrc, *asrc;
-    if constexpr (PREC == GPMPPI_FP32) {
-        zsrc = reinterpret_cast<const v4f *>(g.zs) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const v4f *>(g.alpha + (size_t)o * Mpad);
-    } else {
-        zsrc = reinterpret_cast<const v4f *>(g.zs2) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const v4f *>(g.cza + (size_t)o * Mpad * 2);
-    }
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int slot = threadIdx.x + r * kThreads;
-        v4f val = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (slot < nz) val = zsrc[slot];
-        else if (slot < ns) val = asrc[slot - nz];
-        st.v[r] = val;
-    }
-}
-
-template <int PREC>
-__device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev &g, unsigned char *lds,
-                                            size_t zs_off) {
-    const int ns = staged_slots<PREC>(g.Mpad);
-    v4f *dst = reinterpret_cast<v4f *>(lds + zs_off);
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int slot = threadIdx.x + r * kThreads;
-        if (slot < ns) dst[slot] = st.v[r];
-    }
-}
-
-__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
-    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-    typedef float v2f __attribute__((ext_vector_type(2)));
-    const v2f x = {a, b};
-    const v2bf h = __builtin_convertvector(x, v2bf);   // round to nearest even
-    uint32_t r;
-    __builtin_memcpy(&r, &h, 4);
-    return r;
-}
-
-// One GP output for the B samples of the block; called by all threads with
-// the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
-// next_o replace them before returning (the caller synchronises before the
-// next use).  Returns the sample's GP mean and predictive variance.
-template <int PREC, int G>
-__device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
-                                          bool rev, int rotate, int blk, unsigned char *lds, float *pred,
-                                          float *vred, float &mean_out, float &var_out) {
-    using S = Shapes<PREC, G>;
-    const int Mpad = g.Mpad;
-    const int nchunk = Mpad >> 3;
-    const float4 *zs = reinterpret_cast<const float4 *>(lds + G * kgroup_bytes<PREC>(Mpad));
-    const int grp = sl >> 5, s32 = sl & 31;
-    unsigned char *kg = lds + grp * kgroup_bytes<PREC>(Mpad);
-    float msum = 0.0f;
-    if constexpr (PREC == GPMPPI_FP32) {
-        // exact differences: k = exp2(c2 - sum_d (q_d - zs_d)^2)
-        const float *al = reinterpret_cast<const float *>(zs + Mpad);
-        const float c2 = g.c2[o];
-        for (int c = part; c < nchunk; c += S::parts) {
-            float kv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float4 z = zs[8 * c + e];
-                const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
-                float acc = c2;
-                acc = fmaf(-d0, d0, acc);
-                acc = fmaf(-d1, d1, acc);
-                acc = fmaf(-d2, d2, acc);
-                acc = fmaf(-d3, d3, acc);
-                kv[e] = __builtin_amdgcn_exp2f(acc);
-            }
-            const float4 a0 = *reinterpret_cast<const float4 *>(al + 8 * c);
-            const float4 a1 = *reinterpret_cast<const float4 *>(al + 8 * c + 4);
-            msum = fmaf(kv[0], a0.x, msum);
-            msum = fmaf(kv[1], a0.y, msum);
-            msum = fmaf(kv[2], a0.z, msum);
-            msum = fmaf(kv[3], a0.w, msum);
-            msum = fmaf(kv[4], a1.x, msum);
-            msum = fmaf(kv[5], a1.y, msum);
-            msum = fmaf(kv[6], a1.z, msum);
-            msum = fmaf(kv[7], a1.w, msum);
-            float4 *K = reinterpret_cast<float4 *>(kg) + (size_t)c * 64;
-            K[s32] = make_float4(kv[0], kv[2], kv[4], kv[6]);
-            K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
-        }
-    } else {
-        // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs); its FP32 rounding
-        // (~1e-6 relative in k) is far below the BF16 operand rounding (2^-9)
-        const float4 *cza = zs + Mpad;   // (c2 - |zs|^2, alpha) pairs
-        const float qq = qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3];
-        for (int c = part; c < nchunk; c += S::parts) {
-            float kv[8];
-            float al8[8];
-#pragma unroll
-            for (int e2 = 0; e2 < 4; ++e2) {
-                const float4 ca = cza[4 * c + e2];
-                al8[2 * e2] = ca.y;
-                al8[2 * e2 + 1] = ca.w;
-                const float cz[2] = {ca.x, ca.z};
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int e = 2 * e2 + h;
-                    const float4 z2 = zs[8 * c + e];
-                    float acc = cz[h] - qq;
-                    acc = fmaf(qs[0], z2.x, acc);
-                    acc = fmaf(qs[1], z2.y, acc);
-                    acc = fmaf(qs[2], z2.z, acc);
-                    acc = fmaf(qs[3], z2.w, acc);
-                    kv[e] = __builtin_amdgcn_exp2f(fminf(acc, 64.0f));
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) msum = fmaf(kv[e], al8[e], msum);
-            uint4 hv;
-            hv.x = pack_bf16x2(kv[0], kv[1]);
-            hv.y = pack_bf16x2(kv[2], kv[3]);
-            hv.z = pack_bf16x2(kv[4], kv[5]);
-            hv.w = pack_bf16x2(kv[6], kv[7]);
-            const int idx = (c >> 1) * 64 + s32 + 32 * (c & 1);
-            reinterpret_cast<uint4 *>(kg)[idx] = hv;
-            if constexpr (PREC == GPMPPI_BF16X3) {
-                uint4 lv;
-                lv.x = pack_bf16x2(kv[0] - bf16_to_f32((uint16_t)hv.x), kv[1] - bf16_to_f32((uint16_t)(hv.x >> 16)));
-                lv.y = pack_bf16x2(kv[2] - bf16_to_f32((uint16_t)hv.y), kv[3] - bf16_to_f32((uint16_t)(hv.y >> 16)));
-                lv.z = pack_bf16x2(kv[4] - bf16_to_f32((uint16_t)hv.z), kv[5] - bf16_to_f32((uint16_t)(hv.z >> 16)));
-                lv.w = pack_bf16x2(kv[6] - bf16_to_f32((uint16_t)hv.w), kv[7] - bf16_to_f32((uint16_t)(hv.w >> 16)));
-                reinterpret_cast<uint4 *>(kg + (size_t)Mpad * 64)[idx] = lv;
-            }
-        }
-    }
-    // per-part partial means: the lanes of a part hold distinct samples
-    pred[part * S::B + sl] = msum;
-    __syncthreads();
-    StagedInputs st;
-    if (next_o >= 0) stage_load<PREC>(st, g, next_o);
-
-    // ---- variance contraction on the matrix cores
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int NP = g.NT >> 1;
-    const int rounds = (NP + 3) >> 2;
-    int npairs = rounds;
-    if (wave_pair(w, rounds - 1) >= NP) npairs = rounds - 1;
-    int nit = 0;
-    for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair(w, i) + 2;   // even
-    const int r0 = (rotate && npairs > 0) ? (int)((unsigned)blk % (unsigned)npairs) : 0;
-
-    const unsigned char *kgrp[G];
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
-    // register ring of two iterations (two W blocks each); k operand one iteration ahead
-    WBlock<PREC> ring[2][2];
-    KOp<PREC> kcur[G];
-    v16f acc[2][G];
-    float sq[G];
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-        acc[0][gg] = v16f{};
-        acc[1][gg] = v16f{};
-        sq[gg] = 0.0f;
-    }
-    Cursor pc, mc;   // prefetch and compute cursors
-    if (nit > 0) {
-        cursor_start(pc, w, npairs, r0, rev);
-        cursor_start(mc, w, npairs, r0, rev);
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int b0 = pair_block(pc);
-            load_wblock<PREC>(ring[r][0], g, o, b0, lane);
-            load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-            cursor_next(pc, w, npairs, r0, rev);
-        }
-#pragma unroll
-        for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
-    }
-    for (int base = 0; base < nit; base += 2) {
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const WBlock<PREC> wa = ring[r][0], wb = ring[r][1];
-            if (base + r + 2 < nit) {
-                const int b0 = pair_block(pc);
-                load_wblock<PREC>(ring[r][0], g, o, b0, lane);
-                load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-                cursor_next(pc, w, npairs, r0, rev);
-            }
-            KOp<PREC> kuse[G];
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) kuse[gg] = kcur[gg];
-            const bool pair_end = cursor_next(mc, w, npairs, r0, rev);
-            if (base + r + 1 < nit) {
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
-            }
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                mma_block<PREC>(acc[0][gg], wa, kuse[gg]);
-                mma_block<PREC>(acc[1][gg], wb, kuse[gg]);
-            }
-            if (pair_end) {
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        sq[gg] = fmaf(acc[0][gg][e], acc[0][gg][e], sq[gg]);
-                        sq[gg] = fmaf(acc[1][gg][e], acc[1][gg][e], sq[gg]);
-                    }
-                    acc[0][gg] = v16f{};
-                    acc[1][gg] = v16f{};
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-        sq[gg] += shfl_xor(sq[gg], 32);
-        if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
-    }
-    __syncthreads();
-    if (next_o >= 0) stage_store<PREC>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
-    float v2 = 0.0f, m = 0.0f;
-#pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) v2 += vred[ww * S::B + sl];
-#pragma unroll
-    for (int p = 0; p < S::parts; ++p) m += pred[p * S::B + sl];
-    var_out = g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));
-    mean_out = m;
-}
 
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
 // problem; called by all threads of a workgroup.

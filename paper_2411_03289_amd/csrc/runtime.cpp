@@ -74,6 +74,8 @@ namespace gpmppi {
 gpmppi_status set_error(gpmppi_status st, const char *msg) { return fail(st, "%s", msg); }
 }  // namespace gpmppi
 
+constexpr int kGradMaxMpad = 512;   // the adjoint's LDS plan holds k and r for 32 samples
+
 struct gpmppi_ctx {
     int device = 0;
     gpmppi_params params{};
@@ -86,6 +88,10 @@ struct gpmppi_ctx {
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
     long long w32_stride = 0, wb_stride = 0;
+    float4 *q32 = nullptr;           // dense packed Q = A^-1 per output (differentiation form, Mpad <= 512)
+    long long q_stride = 0;          // float4 per output
+    void *grad_ws = nullptr;         // differentiation-form workspace (grown on demand)
+    size_t grad_ws_bytes = 0;
     float4 *obs = nullptr;
     float4 *seg = nullptr;
     float *seg_inv = nullptr;
@@ -108,6 +114,7 @@ struct gpmppi_ctx {
     std::vector<void *> owned;
 
     ~gpmppi_ctx() {
+        if (grad_ws) (void)hipFree(grad_ws);
         for (void *p : owned) (void)hipFree(p);
     }
 };
@@ -225,6 +232,7 @@ gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
                                c->zs2 + (size_t)o * Mpad * 4, c->cza + (size_t)o * Mpad * 2,
                                c->w32 + o * c->w32_stride, c->wbh + o * c->wb_stride, c->wbl + o * c->wb_stride,
                                nullptr));
+        if (c->q32) HIP_TRY(pack_q(b, M, Mpad, c->q32 + (size_t)o * c->q_stride, nullptr));
         HIP_TRY(hipDeviceSynchronize());
         for (int d = 0; d < 4; ++d) c->gp.scale[o][d] = (float)scale[d];
         c->gp.c2[o] = (float)(2.0 * gp[o].log_sf / std::log(2.0));
@@ -343,6 +351,10 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->w32 = track(dev_alloc<float4>((size_t)2 * c->w32_stride, st));
     c->wbh = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
     c->wbl = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
+    if (Mpad <= kGradMaxMpad) {
+        c->q_stride = (long long)(Mpad / 32) * (Mpad / 32) * 256;
+        c->q32 = track(dev_alloc<float4>((size_t)2 * c->q_stride, st));
+    }
     c->obs = track(dev_alloc<float4>((size_t)std::max(1, c->n_obs), st));
     c->seg = track(dev_alloc<float4>((size_t)std::max(1, P), st));
     c->seg_inv = track(dev_alloc<float>((size_t)std::max(1, P), st));
@@ -1050,6 +1062,89 @@ void gpmppi_batch_destroy(gpmppi_batch *b) { delete b; }
 double gpmppi_norm_quantile(double p) {
     if (!(p > 0.0 && p < 1.0)) return std::nan("");
     return norm_quantile(p);
+}
+
+gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, double tau,
+                          int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
+                          float *costs_d, void *stream) {
+    g_last_error.clear();
+    if (!c || !x0_d || !U_d || !J_d || !dU_d || !dlog_ell_d || !dlog_sf_d) return fail(GPMPPI_E_INVALID, "NULL argument");
+    if (!is_fin(tau) || !(tau > 0.0)) return fail(GPMPPI_E_INVALID, "tau must be finite and > 0");
+    const int K = c->params.K, T = c->params.T, Mpad = c->Mpad;
+    if (checkpoint_every < 1 || checkpoint_every > T)
+        return fail(GPMPPI_E_INVALID, "checkpoint_every must lie in [1, T] (got %d)", checkpoint_every);
+    if (!c->q32)
+        return fail(GPMPPI_E_UNSUPPORTED, "the differentiation form supports M <= %d (padded M is %d)", kGradMaxMpad,
+                    Mpad);
+    if (c->n_terr > 0) return fail(GPMPPI_E_UNSUPPORTED, "the differentiation form has no terrain ensemble");
+    if (c->params.tighten != 0 || c->params.w_goal != 0.0 || c->params.w_term != 0.0)
+        return fail(GPMPPI_E_UNSUPPORTED, "the differentiation form has no goal terms or Step-2 tightening");
+    const int C = checkpoint_every;
+    GradLaunch l{};
+    l.nwg = (K + 31) / 32;
+    const int nck = (T + C - 1) / C;
+    const int nb = (Mpad + 127) / 128;
+    l.npairs = nb * (nb + 1) / 2;
+    const long long TK = (long long)T * K;
+    l.nsplit = (int)std::max(1LL, std::min<long long>({64LL, (512 + 2 * l.npairs - 1) / (2 * l.npairs), (TK + 1) / 2}));
+    l.nbterm = (Mpad + kThreads - 1) / kThreads;
+    // workspace layout (256-byte aligned pieces)
+    size_t off = 0;
+    auto take = [&](size_t nfloat) {
+        const size_t at = off;
+        off += (nfloat * sizeof(float) + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_ck = take((size_t)nck * 20 * K), o_seg = take((size_t)l.nwg * (C + 1) * 28 * 32),
+                 o_R = take((size_t)2 * TK * Mpad), o_G = take((size_t)2 * TK), o_b = take((size_t)l.nwg * 2 * Mpad),
+                 o_h = take((size_t)l.nwg * 10), o_u = take((size_t)l.nwg * T * 2),
+                 o_p = take((size_t)2 * l.npairs * l.nsplit * 5), o_bt = take((size_t)2 * l.nbterm * 5),
+                 o_c = take((size_t)K);
+    if (off > c->grad_ws_bytes) {
+        if (c->grad_ws) (void)hipFree(c->grad_ws);
+        c->grad_ws = nullptr;
+        c->grad_ws_bytes = 0;
+        if (hipMalloc(&c->grad_ws, off) != hipSuccess) {
+            c->grad_ws = nullptr;
+            return fail(GPMPPI_E_NOMEM, "hipMalloc of the %zu-byte gradient workspace failed", off);
+        }
+        c->grad_ws_bytes = off;
+    }
+    char *ws = static_cast<char *>(c->grad_ws);
+    GradArgs a{};
+    a.gp = c->gp;
+    a.geo = c->geo;
+    a.cw = c->cw;
+    a.dyn = c->dyn;
+    a.noise = noise_of(c);
+    a.noise.key0 = (uint32_t)seed;
+    a.noise.key1 = (uint32_t)(seed >> 32);
+    a.K = K;
+    a.T = T;
+    a.C = C;
+    a.nck = nck;
+    a.inv_tau = (float)(1.0 / tau);
+    a.inv_K = 1.0f / (float)K;
+    a.q32 = c->q32;
+    a.q_stride = c->q_stride;
+    a.x0 = x0_d;
+    a.U = U_d;
+    a.costs = costs_d ? costs_d : reinterpret_cast<float *>(ws + o_c);
+    a.ckpt = reinterpret_cast<float *>(ws + o_ck);
+    a.seg = reinterpret_cast<float *>(ws + o_seg);
+    a.R = reinterpret_cast<float *>(ws + o_R);
+    a.Gw = reinterpret_cast<float *>(ws + o_G);
+    a.bpart = reinterpret_cast<float *>(ws + o_b);
+    a.hpart = reinterpret_cast<float *>(ws + o_h);
+    a.upart = reinterpret_cast<float *>(ws + o_u);
+    l.ppart = reinterpret_cast<float *>(ws + o_p);
+    l.bterm = reinterpret_cast<float *>(ws + o_bt);
+    l.J = J_d;
+    l.dU = dU_d;
+    l.dlog_ell = dlog_ell_d;
+    l.dlog_sf = dlog_sf_d;
+    HIP_TRY(launch_grad(a, l, (hipStream_t)stream));
+    return GPMPPI_OK;
 }
 
 void gpmppi_destroy(gpmppi_ctx *c) { delete c; }

@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_batch_step": [vp, vp, vp, u64, vp, vp, vp, vp],
         "gpmppi_batch_closed_loop": [vp, vp, vp, u64, i32, f64, vp, i32, vp],
         "gpmppi_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
+        "gpmppi_grad": [vp, vp, vp, u64, f64, i32, vp, vp, vp, vp, vp, vp],
         "gpmppi_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_batch_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
@@ -439,6 +440,73 @@ def gpmppi_batch_closed_loop(b: Batch, x, U, seed0: int, n_steps: int, amplitude
                                           ctypes.c_uint64(seed0), int(n_steps), float(amplitude),
                                           _dev(x_hist, 5 * b.n * (n_steps + 1), "x_hist", optional=True),
                                           int(bool(use_graph)), _stream(stream)))
+
+
+def gpmppi_grad(ctx: Context, x0, U, seed: int, tau: float, checkpoint_every: int, J, dU, dlog_ell, dlog_sf,
+                costs=None, stream=None):
+    K, T = ctx.params["K"], ctx.params["T"]
+    _check(lib().gpmppi_grad(ctx.handle, _dev(x0, 5, "x0"), _dev(U, 2 * T, "U"), ctypes.c_uint64(seed), float(tau),
+                             int(checkpoint_every), _dev(J, 1, "J"), _dev(dU, 2 * T, "dU"),
+                             _dev(dlog_ell, 8, "dlog_ell"), _dev(dlog_sf, 2, "dlog_sf"),
+                             _dev(costs, K, "costs", optional=True), _stream(stream)))
+
+
+class GradProblem:
+    """A context for the differentiation form: holds the GP data to rebuild the
+    GP when the hyperparameters change, the start state and the seed."""
+
+    def __init__(self, problem, seed=None, tau: float = 0.05, checkpoint_every: int = 10, x0=None):
+        import torch
+        self.problem = problem
+        self.ctx = gpmppi_init(problem, FP32)
+        self.seed = problem.seed if seed is None else seed
+        self.tau = tau
+        self.checkpoint_every = min(checkpoint_every, problem.T)
+        self.x0 = torch.as_tensor(np.asarray(problem.x0 if x0 is None else x0), dtype=torch.float32, device="cuda")
+        self._hyper = (np.array(problem.log_ell, dtype=np.float64), np.array(problem.log_sf, dtype=np.float64))
+
+    def set_hyper(self, log_ell, log_sf):
+        le = np.asarray(log_ell, dtype=np.float64).reshape(2, 4)
+        ls = np.asarray(log_sf, dtype=np.float64).reshape(2)
+        if np.array_equal(le, self._hyper[0]) and np.array_equal(ls, self._hyper[1]):
+            return
+        import copy
+        pr = copy.copy(self.problem)
+        pr.log_ell, pr.log_sf = le, ls
+        gpmppi_set_gp(self.ctx, pr)
+        self._hyper = (le, ls)
+
+    def evaluate(self, U, log_ell, log_sf):
+        """(J, dU, dlog_ell, dlog_sf) as device tensors."""
+        import torch
+        self.set_hyper(log_ell, log_sf)
+        f32 = dict(dtype=torch.float32, device="cuda")
+        U = torch.as_tensor(U, **f32).contiguous()
+        J, dU = torch.empty(1, **f32), torch.empty_like(U)
+        dle, dls = torch.empty((2, 4), **f32), torch.empty(2, **f32)
+        gpmppi_grad(self.ctx, self.x0, U, self.seed, self.tau, self.checkpoint_every, J, dU, dle, dls)
+        return J, dU, dle, dls
+
+
+def expected_cost(gp: GradProblem, U, log_ell, log_sf):
+    """J(U, log_ell, log_sf) as a differentiable torch scalar (the adjoint rollout
+    supplies the gradient)."""
+    import torch
+
+    class _ExpectedCost(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, U_, le_, ls_):
+            J, dU, dle, dls = gp.evaluate(U_.detach(), le_.detach().cpu().numpy(), ls_.detach().cpu().numpy())
+            fctx.save_for_backward(dU.to(U_.device, U_.dtype), dle.to(le_.device, le_.dtype),
+                                   dls.to(ls_.device, ls_.dtype))
+            return J[0].to(U_.device, U_.dtype)
+
+        @staticmethod
+        def backward(fctx, gJ):
+            dU, dle, dls = fctx.saved_tensors
+            return gJ.to(dU.device) * dU, gJ.to(dle.device) * dle, gJ.to(dls.device) * dls
+
+    return _ExpectedCost.apply(U, log_ell, log_sf)
 
 
 def gpmppi_tune(ctx: Context, x0, U, seed: int, reps: int = 3, stream=None) -> dict:

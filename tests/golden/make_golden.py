@@ -9,6 +9,14 @@ Output (c2_oracle.npz): the first MPPI iteration of workload 2 (K=16384,
 T=100, M=1024, 50 obstacles, figure-eight track) from its own start state,
 nominal controls and seed: U_new [T,2], costs S [K], weights w [K], and the
 per-sample indicator flip budget at margin band 1e-4 m [K].
+
+    python tests/golden/make_golden.py c4
+
+Output (c4_grad.npz): the differentiation form on workload 4 (K=4096, T=50,
+M=512, 20 obstacles, figure-eight track, tau = 0.05 m) from its start state,
+nominal controls and seed: J, dJ/dU [T,2], dJ/dlog_ell [2,4], dJ/dlog_sf [2]
+and the smoothed per-sample costs [K], by float64 reverse-mode autodiff of the
+oracle, accumulated over sample chunks (J is a sample mean).
 """
 import os
 import sys
@@ -46,7 +54,31 @@ def golden_c2():
                         flip_band=FLIP_BAND)
 
 
+def golden_c4(tau=0.05, chunk=512):
+    import torch
+
+    from oracle import grad as OG
+    pr = W.make_config(4)
+    Ut, le, ls = OG.leaves(pr)
+    costs = np.empty(pr.K)
+    gU, gl, gs = np.zeros((pr.T, 2)), np.zeros((2, 4)), np.zeros(2)
+    t0 = time.time()
+    for a in range(0, pr.K, chunk):
+        ids = np.arange(a, min(pr.K, a + chunk))
+        S = OG.smoothed_costs(pr, Ut, le, ls, pr.seed, tau, sample_ids=ids)
+        g = torch.autograd.grad(S.sum() / pr.K, (Ut, le, ls))
+        gU += g[0].numpy()
+        gl += g[1].numpy()
+        gs += g[2].numpy()
+        costs[ids] = S.detach().numpy()
+        print(f"samples {ids[-1] + 1}/{pr.K}  {time.time() - t0:.0f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c4_grad.npz"), J=costs.mean(), dU=gU, dlog_ell=gl, dlog_sf=gs,
+                        costs=costs, tau=tau)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
     if "c2" in which:
         golden_c2()
+    if "c4" in which:
+        golden_c4()

@@ -142,3 +142,7 @@ def test_tuning_struct_and_null_handles(L):
         assert fn(None, ctypes.byref(t)) == -1
     assert L.gpmppi_tune(None, None, None, 0, 1, None, None) == -1
     assert L.gpmppi_batch_tune(None, None, None, 0, 1, None, None) == -1
+
+
+def test_grad_entry_point_rejects_null_context(L):
+    assert L.gpmppi_grad(None, None, None, 0, 0.05, 10, None, None, None, None, None, None) == -1
