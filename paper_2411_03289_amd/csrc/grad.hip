@@ -28,6 +28,7 @@
 // b = sum mbar r and P = sum s2bar r r^T over all sample-steps.  b is summed in
 // registers; P is formed by grad_syrk_kernel from the stored r (FP32
 // [T K][Mpad] per output) and contracted on the fly with dA/dtheta.
+#include "adjoint_step.hpp"
 #include "gp_tiles.hpp"
 
 namespace gpmppi {
@@ -39,126 +40,6 @@ constexpr int kParts = 8;        // loop splitters
 constexpr int kSegF = 28;        // per step: x 5, p 15, u 2, m 2, s2 2, latent-positive flags 2
 constexpr int kCkF = 20;         // per checkpoint: x 5, p 15
 constexpr float kLn2 = 0.69314718055994531f;
-
-// p index: 00 01 02 03 04 11 12 13 14 22 23 24 33 34 44
-struct Jac {
-    float a02, a03, a12, a13;
-};
-
-__device__ __forceinline__ void cov_forward(const float p[15], const Jac &J, float a24, float a33, float a44,
-                                            float e3, float e4, float P[15]) {
-    const float p00 = p[0], p01 = p[1], p02 = p[2], p03 = p[3], p04 = p[4], p11 = p[5], p12 = p[6], p13 = p[7],
-                p14 = p[8], p22 = p[9], p23 = p[10], p24 = p[11], p33 = p[12], p34 = p[13], p44 = p[14];
-    const float b00 = p00 + J.a02 * p02 + J.a03 * p03, b01 = p01 + J.a02 * p12 + J.a03 * p13,
-                b02 = p02 + J.a02 * p22 + J.a03 * p23, b03 = p03 + J.a02 * p23 + J.a03 * p33,
-                b04 = p04 + J.a02 * p24 + J.a03 * p34;
-    const float b11 = p11 + J.a12 * p12 + J.a13 * p13, b12 = p12 + J.a12 * p22 + J.a13 * p23,
-                b13 = p13 + J.a12 * p23 + J.a13 * p33, b14 = p14 + J.a12 * p24 + J.a13 * p34;
-    const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
-    const float b33 = a33 * p33, b34 = a33 * p34, b44 = a44 * p44;
-    P[0] = b00 + J.a02 * b02 + J.a03 * b03;
-    P[1] = b01 + J.a12 * b02 + J.a13 * b03;
-    P[2] = b02 + a24 * b04;
-    P[3] = a33 * b03;
-    P[4] = a44 * b04;
-    P[5] = b11 + J.a12 * b12 + J.a13 * b13;
-    P[6] = b12 + a24 * b14;
-    P[7] = a33 * b13;
-    P[8] = a44 * b14;
-    P[9] = b22 + a24 * b24;
-    P[10] = a33 * b23;
-    P[11] = a44 * b24;
-    P[12] = a33 * b33 + e3;
-    P[13] = a44 * b34;
-    P[14] = a44 * b44 + e4;
-}
-
-// Reverse of cov_forward: Pb (adjoint of P) -> pb (adjoint of p, overwritten),
-// adjoints of a02 a03 a12 a13 added to Jb, of e3 and e4 returned.
-__device__ __forceinline__ void cov_backward(const float p[15], const Jac &J, float a24, float a33, float a44,
-                                             const float Pb[15], float pb[15], Jac &Jb, float &e3b, float &e4b) {
-    const float p02 = p[2], p03 = p[3], p12 = p[6], p13 = p[7], p22 = p[9], p23 = p[10], p24 = p[11], p33 = p[12],
-                p34 = p[13];
-    // forward intermediates needed by the reverse
-    const float b02 = p02 + J.a02 * p22 + J.a03 * p23, b03 = p03 + J.a02 * p23 + J.a03 * p33;
-    const float b12 = p12 + J.a12 * p22 + J.a13 * p23, b13 = p13 + J.a12 * p23 + J.a13 * p33;
-    float bb00 = 0, bb01 = 0, bb02 = 0, bb03 = 0, bb04 = 0, bb11 = 0, bb12 = 0, bb13 = 0, bb14 = 0, bb22 = 0,
-          bb23 = 0, bb24 = 0, bb33 = 0, bb34 = 0, bb44 = 0;
-    // P00 = b00 + a02 b02 + a03 b03
-    bb00 += Pb[0]; bb02 += J.a02 * Pb[0]; bb03 += J.a03 * Pb[0];
-    Jb.a02 += b02 * Pb[0]; Jb.a03 += b03 * Pb[0];
-    // P01 = b01 + a12 b02 + a13 b03
-    bb01 += Pb[1]; bb02 += J.a12 * Pb[1]; bb03 += J.a13 * Pb[1];
-    Jb.a12 += b02 * Pb[1]; Jb.a13 += b03 * Pb[1];
-    // P02 = b02 + a24 b04; P03 = a33 b03; P04 = a44 b04
-    bb02 += Pb[2]; bb04 += a24 * Pb[2];
-    bb03 += a33 * Pb[3];
-    bb04 += a44 * Pb[4];
-    // P11 = b11 + a12 b12 + a13 b13
-    bb11 += Pb[5]; bb12 += J.a12 * Pb[5]; bb13 += J.a13 * Pb[5];
-    Jb.a12 += b12 * Pb[5]; Jb.a13 += b13 * Pb[5];
-    // P12 = b12 + a24 b14; P13 = a33 b13; P14 = a44 b14
-    bb12 += Pb[6]; bb14 += a24 * Pb[6];
-    bb13 += a33 * Pb[7];
-    bb14 += a44 * Pb[8];
-    // P22 = b22 + a24 b24; P23 = a33 b23; P24 = a44 b24
-    bb22 += Pb[9]; bb24 += a24 * Pb[9];
-    bb23 += a33 * Pb[10];
-    bb24 += a44 * Pb[11];
-    // P33 = a33 b33 + e3; P34 = a44 b34; P44 = a44 b44 + e4
-    bb33 += a33 * Pb[12]; e3b = Pb[12];
-    bb34 += a44 * Pb[13];
-    bb44 += a44 * Pb[14]; e4b = Pb[14];
-    // b rows -> p
-    float q[15] = {};
-    // b00 = p00 + a02 p02 + a03 p03
-    q[0] += bb00; q[2] += J.a02 * bb00; q[3] += J.a03 * bb00; Jb.a02 += p02 * bb00; Jb.a03 += p03 * bb00;
-    // b01 = p01 + a02 p12 + a03 p13
-    q[1] += bb01; q[6] += J.a02 * bb01; q[7] += J.a03 * bb01; Jb.a02 += p12 * bb01; Jb.a03 += p13 * bb01;
-    // b02 = p02 + a02 p22 + a03 p23
-    q[2] += bb02; q[9] += J.a02 * bb02; q[10] += J.a03 * bb02; Jb.a02 += p22 * bb02; Jb.a03 += p23 * bb02;
-    // b03 = p03 + a02 p23 + a03 p33
-    q[3] += bb03; q[10] += J.a02 * bb03; q[12] += J.a03 * bb03; Jb.a02 += p23 * bb03; Jb.a03 += p33 * bb03;
-    // b04 = p04 + a02 p24 + a03 p34
-    q[4] += bb04; q[11] += J.a02 * bb04; q[13] += J.a03 * bb04; Jb.a02 += p24 * bb04; Jb.a03 += p34 * bb04;
-    // b11 = p11 + a12 p12 + a13 p13
-    q[5] += bb11; q[6] += J.a12 * bb11; q[7] += J.a13 * bb11; Jb.a12 += p12 * bb11; Jb.a13 += p13 * bb11;
-    // b12 = p12 + a12 p22 + a13 p23
-    q[6] += bb12; q[9] += J.a12 * bb12; q[10] += J.a13 * bb12; Jb.a12 += p22 * bb12; Jb.a13 += p23 * bb12;
-    // b13 = p13 + a12 p23 + a13 p33
-    q[7] += bb13; q[10] += J.a12 * bb13; q[12] += J.a13 * bb13; Jb.a12 += p23 * bb13; Jb.a13 += p33 * bb13;
-    // b14 = p14 + a12 p24 + a13 p34
-    q[8] += bb14; q[11] += J.a12 * bb14; q[13] += J.a13 * bb14; Jb.a12 += p24 * bb14; Jb.a13 += p34 * bb14;
-    // b22 = p22 + a24 p24; b23 = p23 + a24 p34; b24 = p24 + a24 p44
-    q[9] += bb22; q[11] += a24 * bb22;
-    q[10] += bb23; q[13] += a24 * bb23;
-    q[11] += bb24; q[14] += a24 * bb24;
-    // b33 = a33 p33; b34 = a33 p34; b44 = a44 p44
-    q[12] += a33 * bb33;
-    q[13] += a33 * bb34;
-    q[14] += a44 * bb44;
-#pragma unroll
-    for (int i = 0; i < 15; ++i) pb[i] = q[i];
-}
-
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
-
-// Largest eigenvalue of [[a, b], [b, c]] and its partial derivatives (the
-// root's derivative taken as 0 where the root is 0).
-__device__ __forceinline__ float lmax_grad(float a, float b, float c, float &da, float &db, float &dc) {
-    const float h = 0.5f * (a - c);
-    const float s = sqrtf(h * h + b * b);
-    if (s > 0.0f) {
-        da = 0.5f + 0.5f * h / s;
-        dc = 0.5f - 0.5f * h / s;
-        db = b / s;
-    } else {
-        da = 0.5f;
-        dc = 0.5f;
-        db = 0.0f;
-    }
-    return 0.5f * (a + c) + s;
-}
 
 }  // namespace
 
@@ -304,34 +185,6 @@ __device__ __forceinline__ void constraint_scan(const Geometry &geo, float X, fl
     }
 }
 
-// Lane distance and its gradient in (X, Y).
-__device__ __forceinline__ float lane_dist_grad(const Geometry &geo, float X, float Y, float best_all, int iseg,
-                                                float &gx, float &gy) {
-    gx = 0.0f;
-    gy = 0.0f;
-    if (geo.path_kind == 0) {
-        const float dx = X - geo.cx, dyy = Y - geo.cy;
-        const float rho = sqrtf(dx * dx + dyy * dyy);
-        const float d = rho - geo.R;
-        if (rho > 0.0f && d != 0.0f) {
-            const float sg = d > 0.0f ? 1.0f : -1.0f;
-            gx = sg * dx / rho;
-            gy = sg * dyy / rho;
-        }
-        return fabsf(d);
-    }
-    const float dl = sqrtf(best_all);
-    if (iseg >= 0 && dl > 0.0f) {
-        const float4 sgm = geo.seg[iseg];
-        const float rx = X - sgm.x, ry = Y - sgm.y;
-        float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[iseg];
-        t = fminf(fmaxf(t, 0.0f), 1.0f);
-        gx = (rx - t * sgm.z) / dl;
-        gy = (ry - t * sgm.w) / dl;
-    }
-    return dl;
-}
-
 __device__ __forceinline__ void seg_put(float *base, int f, float v) { base[f * kB] = v; }
 
 }  // namespace
@@ -448,20 +301,14 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             }
             if (first) {
                 // smoothed stage cost on (x_{k+1}, Sigma_{k+1})
-                const float sa = p[0], sb = p[1], sc = p[5];
                 float da, db, dc;
-                const float lmax = lmax_grad(sa, sb, sc, da, db, dc);
+                const float lmax = lmax_grad(p[0], p[1], p[5], da, db, dc);
                 float best_all, om_all;
                 int iseg, iobs;
-                constraint_scan(geo, X, Y, sa, sb, sc, lmax, part, sl, vb, ib, vo, io, best_all, iseg, om_all,
+                constraint_scan(geo, X, Y, p[0], p[1], p[5], lmax, part, sl, vb, ib, vo, io, best_all, iseg, om_all,
                                 iobs);
-                float gx, gy;
-                const float dl = lane_dist_grad(geo, X, Y, best_all, iseg, gx, gy);
-                const float rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
-                const float dv = cw.v_des - v;
-                float c = cw.w_var * (s2[0] + s2[1]) + cw.w_dev * (dl * geo.inv_half_width) + cw.w_speed * (dv * dv);
-                c += cw.w_lane * disc * sigmoidf((dl - rbar) * a.inv_tau);
-                if (geo.n_obs > 0) c += cw.w_obs * sigmoidf(-om_all * a.inv_tau);
+                const float x1[5] = {X, Y, th, v, w_};
+                const float c = smoothed_stage(geo, cw, a.inv_tau, disc, x1, p, s2, iseg, iobs);
                 const float yk = c - Sc;
                 const float tk = S_ + yk;
                 Sc = (tk - S_) - yk;
@@ -485,93 +332,35 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
         for (int k = k1 - 1; k >= k0; --k) {
             const float *e1 = segw + (size_t)(k + 1 - k0) * kSegF * kB;   // x_{k+1}, p_{k+1}
             const float *e0 = segw + (size_t)(k - k0) * kSegF * kB;       // x_k, p_k, u, m, s2, flags
-            const float X1 = e1[0], Y1 = e1[kB], v1 = e1[3 * kB];
-            const float sa = e1[(5 + 0) * kB], sb = e1[(5 + 1) * kB], sc = e1[(5 + 5) * kB];
-            const float thk = e0[2 * kB], vk = e0[3 * kB], wk = e0[4 * kB];
+            const float vk = e0[3 * kB], wk = e0[4 * kB];
             float pk[15];
 #pragma unroll
             for (int i = 0; i < 15; ++i) pk[i] = e0[(5 + i) * kB];
             const float ux = e0[20 * kB], uy = e0[21 * kB];
             const float flag[2] = {e0[26 * kB], e0[27 * kB]};
 
-            // ---- stage cost adjoint at (x_{k+1}, Sigma_{k+1}, s2_k)
+            float x1[5], p1[15], xk[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                x1[i] = e1[i * kB];
+                xk[i] = e0[i * kB];
+            }
+#pragma unroll
+            for (int i = 0; i < 15; ++i) p1[i] = e1[(5 + i) * kB];
             float da, db, dc;
-            const float lmax = lmax_grad(sa, sb, sc, da, db, dc);
+            const float lmax = lmax_grad(p1[0], p1[1], p1[5], da, db, dc);
             float best_all, om_all;
             int iseg, iobs;
-            constraint_scan(geo, X1, Y1, sa, sb, sc, lmax, part, sl, vb, ib, vo, io, best_all, iseg, om_all, iobs);
-            float gx, gy;
-            const float dl = lane_dist_grad(geo, X1, Y1, best_all, iseg, gx, gy);
-            const float sq = sqrtf(fmaxf(lmax, 0.0f));
-            const float rbar = geo.half_width - geo.c_p * sq;
+            constraint_scan(geo, x1[0], x1[1], p1[0], p1[1], p1[5], lmax, part, sl, vb, ib, vo, io, best_all, iseg,
+                            om_all, iobs);
             float discount_k = 1.0f;
             for (int i = 0; i < k; ++i) discount_k *= cw.discount;
-            float s2b[2] = {cbar * cw.w_var, cbar * cw.w_var};
-            float lamb = 0.0f;   // adjoint of lambda_max(Sigma_XY)
-            float dlb = cbar * cw.w_dev * geo.inv_half_width;
-            {
-                const float sL = sigmoidf((dl - rbar) * a.inv_tau);
-                const float gL = cbar * cw.w_lane * discount_k * sL * (1.0f - sL) * a.inv_tau;
-                dlb += gL;
-                if (sq > 0.0f) lamb += -gL * (-geo.c_p) * 0.5f / sq;
-            }
-            float Xb1 = gx * dlb, Yb1 = gy * dlb;
-            float Sab = 0.0f, Sbb = 0.0f, Scb = 0.0f;
-            if (geo.n_obs > 0 && iobs >= 0) {
-                const float sO = sigmoidf(-om_all * a.inv_tau);
-                const float omb = -cbar * cw.w_obs * sO * (1.0f - sO) * a.inv_tau;
-                const float4 ob = geo.obs[iobs];
-                const float dx = X1 - ob.x, dyy = Y1 - ob.y;
-                const float rho2 = dx * dx + dyy * dyy;
-                const float rho = sqrtf(rho2);
-                float var;
-                if (rho > 0.0f) {
-                    var = (sa * dx * dx + 2.0f * sb * dx * dyy + sc * dyy * dyy) / rho2;
-                    Xb1 += omb * dx / rho;
-                    Yb1 += omb * dyy / rho;
-                } else {
-                    var = lmax;
-                }
-                const float sv = sqrtf(fmaxf(var, 0.0f));
-                const float varb = sv > 0.0f ? omb * (-geo.z_p) * 0.5f / sv : 0.0f;
-                if (rho > 0.0f) {
-                    Xb1 += varb * 2.0f * (sa * dx + sb * dyy - var * dx) / rho2;
-                    Yb1 += varb * 2.0f * (sb * dx + sc * dyy - var * dyy) / rho2;
-                    Sab += varb * dx * dx / rho2;
-                    Sbb += varb * 2.0f * dx * dyy / rho2;
-                    Scb += varb * dyy * dyy / rho2;
-                } else {
-                    lamb += varb;
-                }
-            }
-            Sab += lamb * da;
-            Sbb += lamb * db;
-            Scb += lamb * dc;
-            // adjoint of x_{k+1}, Sigma_{k+1}: carried part plus this stage's
-            const float Xn_b = xb[0] + Xb1, Yn_b = xb[1] + Yb1, thn_b = xb[2];
-            const float vn_b = xb[3] + cbar * cw.w_speed * (-2.0f) * (cw.v_des - v1), wn_b = xb[4];
-            pb[0] += Sab;
-            pb[1] += Sbb;
-            pb[5] += Scb;
-
-            // ---- covariance adjoint
-            float sth, cth;
-            sincosf(thk, &sth, &cth);
-            const Jac Jk{-dt * vk * sth, dt * cth, dt * vk * cth, dt * sth};
-            Jac Jb{0.0f, 0.0f, 0.0f, 0.0f};
-            float e3b, e4b, pbk[15];
-            cov_backward(pk, Jk, dt, dy.a33, dy.a44, pb, pbk, Jb, e3b, e4b);
-            s2b[0] += dt * dt * e3b;
-            s2b[1] += dt * dt * e4b;
-
-            // ---- Euler step adjoint (x_{k+1} = f(x_k, u, m)) and the Jacobian's
-            float thb = -Xn_b * dt * vk * sth + Yn_b * dt * vk * cth + thn_b;
-            float vbk = Xn_b * dt * cth + Yn_b * dt * sth + vn_b * (1.0f - dy.dt_tau_v);
-            float wbk = thn_b * dt + wn_b * (1.0f - dy.dt_tau_w);
-            float uxb = vn_b * dy.dt_tau_v, uyb = wn_b * dy.dt_tau_w;
-            const float mb[2] = {vn_b * dt, wn_b * dt};
-            thb += Jb.a02 * (-dt * vk * cth) + Jb.a03 * (-dt * sth) + Jb.a12 * (-dt * vk * sth) + Jb.a13 * (dt * cth);
-            vbk += Jb.a02 * (-dt * sth) + Jb.a12 * (dt * cth);
+            StepAdj sa_out;
+            step_adjoint(geo, cw, dy, a.inv_tau, cbar, discount_k, xk, pk, x1, p1, iseg, iobs, xb, pb, sa_out);
+            float vbk = xb[3], wbk = xb[4];
+            float uxb = sa_out.ub[0], uyb = sa_out.ub[1];
+            const float mb[2] = {sa_out.mb[0], sa_out.mb[1]};
+            const float s2b[2] = {sa_out.s2b[0], sa_out.s2b[1]};
 
             // ---- GP adjoint, both outputs
             const float qk[4] = {vk, wk, ux, uy};
@@ -674,13 +463,8 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                     a.upart[((size_t)blk * T + k) * 2 + tid] = sum;
                 }
             }
-            xb[0] = Xn_b;
-            xb[1] = Yn_b;
-            xb[2] = thb;
             xb[3] = vbk;
             xb[4] = wbk;
-#pragma unroll
-            for (int i = 0; i < 15; ++i) pb[i] = pbk[i];
         }
     }
     (void)np;
