@@ -9,8 +9,8 @@ dynamics, covariance, chance constraints, costs) + weights + control update,
 with every input resident in device memory.
 
 Before timing, the library's autotuner picks each form's launch shape
-(sample groups per workgroup, start of the walk over W); the choice is
-reported per form.
+(sample groups per workgroup, start of the walk over W, waves per
+workgroup); the choice is reported per form.
 
 Forms: fp32 (FP32 matrix cores), bf16x3 (hi+lo BF16 splits), bf16 (plain
 BF16) for the variance contraction k^T (K + sn^2 I)^-1 k.  Each form is timed
@@ -37,8 +37,9 @@ U_ERR_BAR = 1e-3
 # HBM bytes per rollout launch at this workload: rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 1 GiB device copy in the same runs), taken
 # on the kernel sources whose SHA-256 is given; reported only while they match.
-KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd/csrc/device_common.hpp",
-                  "paper_2411_03289_amd/csrc/kernels.hpp", "paper_2411_03289_amd/build.py"]
+KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd/csrc/gp_tiles.hpp",
+                  "paper_2411_03289_amd/csrc/device_common.hpp", "paper_2411_03289_amd/csrc/kernels.hpp",
+                  "paper_2411_03289_amd/build.py"]
 MEASURED_TRAFFIC = {
     "sources_sha256": "cf634db2e466e4a69501c7346365f6cf15381a1891cc3e23858399a675ee3d98",
     "bytes": {"fp32": 578524 * 1024, "bf16x3": 545444 * 1024, "bf16": 18229 * 1024},
@@ -157,7 +158,7 @@ def main():
         results[name] = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall / args.steps,
                              sample_steps_per_s=K * T / (ms * 1e-3), rollout_kernel_ms=rollout_ms,
                              u_err_vs_fp64=u_err,
-                             shape={k: shape[k] for k in ("groups", "rotate")})
+                             shape={k: shape[k] for k in ("groups", "rotate", "waves")})
         log(f"[bench] form={name} {ms:.3f} ms/step rollout {rollout_ms:.3f} ms U err {u_err}")
         del ctx
 

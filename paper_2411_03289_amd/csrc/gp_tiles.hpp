@@ -127,9 +127,11 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
     }
 }
 
-// Pair list of a wave: round i holds pairs 4i .. 4i+3, assigned in snake
-// order so that the summed pair lengths (2u + 2) balance across waves.
-__device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? 4 * i + 3 - w : 4 * i + w; }
+// Pair list of wave w of NW: round i holds pairs NW i .. NW i + NW - 1,
+// assigned in snake order so that the summed pair lengths (2u + 2) balance
+// across waves.
+template <int NW>
+__device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? NW * i + NW - 1 - w : NW * i + w; }
 
 // Position in a wave's iteration sequence: n pairs visited so far, list
 // index i = (r0 + n) mod npairs (forward) or (r0 - 1 - n) mod npairs
@@ -140,21 +142,24 @@ struct Cursor {
     int n, i, u, it;
 };
 
+template <int NW>
 __device__ __forceinline__ void cursor_set(Cursor &c, int w, int npairs, int r0, bool rev) {
     int i = rev ? r0 - 1 - c.n : r0 + c.n;
     i %= npairs;
     if (i < 0) i += npairs;
     c.i = i;
-    c.u = wave_pair(w, i);
+    c.u = wave_pair<NW>(w, i);
     c.it = rev ? 2 * c.u + 1 : 0;
 }
 
+template <int NW>
 __device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, int r0, bool rev) {
     c.n = 0;
-    cursor_set(c, w, npairs, r0, rev);
+    cursor_set<NW>(c, w, npairs, r0, rev);
 }
 
 // Advances; returns true when the iteration just left closed its pair.
+template <int NW>
 __device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0, bool rev) {
     if (!rev) {
         if (++c.it <= 2 * c.u + 1) return false;
@@ -162,7 +167,7 @@ __device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0
         if (--c.it >= 0) return false;
     }
     ++c.n;
-    cursor_set(c, w, npairs, r0, rev);
+    cursor_set<NW>(c, w, npairs, r0, rev);
     return true;
 }
 
@@ -172,10 +177,13 @@ __device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (
 template <int PREC>
 __host__ __device__ constexpr int staged_slots(int Mpad);
 
-template <int PREC, int G>
+template <int PREC, int G, int NW = kWaves>
 struct Shapes {
-    static constexpr int B = 32 * G;                 // samples per block
-    static constexpr int parts = kWaves * (2 / G);   // loop splitters: waves (x half-waves for G = 1)
+    static constexpr int B = 32 * G;              // samples per block
+    static constexpr int waves = NW;              // wave64s per workgroup
+    static constexpr int threads = 64 * NW;
+    static constexpr int parts = NW * (2 / G);    // loop splitters: waves (x half-waves for G = 1)
+    static constexpr int stage_iters = (1536 + threads - 1) / threads;   // staged-input slots per thread
 };
 
 // Dynamic LDS layout: [G k-operand groups][zs: Mpad float4][alpha: Mpad float]
@@ -190,7 +198,7 @@ __host__ __device__ constexpr size_t dyn_lds_bytes(int Mpad) {
 //   FP32:        zs [Mpad] then alpha [Mpad / 4]            (20 B per point)
 //   BF16 forms:  2 zs [Mpad] then (c2 - |zs|^2, alpha) [Mpad / 2]  (24 B per point)
 // held in registers between their global load and their store to LDS; thread
-// t owns slots t, t + 256, ... (at most 1536 slots for Mpad <= 1024).
+// t of T owns slots t, t + T, ... (at most 1536 slots for Mpad <= 1024).
 template <int PREC>
 __host__ __device__ constexpr int staged_slots(int Mpad) {
     return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : Mpad + (Mpad >> 1);
@@ -202,7 +210,7 @@ struct StagedInputs {
     v4f v[6];
 };
 
-template <int PREC>
+template <int PREC, int NW = kWaves>
 __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
     const int Mpad = g.Mpad, nz = Mpad, ns = staged_slots<PREC>(Mpad);
     const v4f *zsrc, *asrc;
@@ -214,8 +222,8 @@ __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int
         asrc = reinterpret_cast<const v4f *>(g.cza + (size_t)o * Mpad * 2);
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int slot = threadIdx.x + r * kThreads;
+    for (int r = 0; r < Shapes<PREC, 1, NW>::stage_iters; ++r) {
+        const int slot = threadIdx.x + r * (64 * NW);
         v4f val = {0.0f, 0.0f, 0.0f, 0.0f};
         if (slot < nz) val = zsrc[slot];
         else if (slot < ns) val = asrc[slot - nz];
@@ -223,14 +231,14 @@ __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int
     }
 }
 
-template <int PREC>
+template <int PREC, int NW = kWaves>
 __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev &g, unsigned char *lds,
                                             size_t zs_off) {
     const int ns = staged_slots<PREC>(g.Mpad);
     v4f *dst = reinterpret_cast<v4f *>(lds + zs_off);
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int slot = threadIdx.x + r * kThreads;
+    for (int r = 0; r < Shapes<PREC, 1, NW>::stage_iters; ++r) {
+        const int slot = threadIdx.x + r * (64 * NW);
         if (slot < ns) dst[slot] = st.v[r];
     }
 }
@@ -249,11 +257,11 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
 // the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
 // next_o replace them before returning (the caller synchronises before the
 // next use).  Returns the sample's GP mean and predictive variance.
-template <int PREC, int G>
+template <int PREC, int G, int NW = kWaves>
 __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
                                           bool rev, int rotate, int blk, unsigned char *lds, float *pred,
                                           float *vred, float &mean_out, float &var_out) {
-    using S = Shapes<PREC, G>;
+    using S = Shapes<PREC, G, NW>;
     const int Mpad = g.Mpad;
     const int nchunk = Mpad >> 3;
     const float4 *zs = reinterpret_cast<const float4 *>(lds + G * kgroup_bytes<PREC>(Mpad));
@@ -340,17 +348,17 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     pred[part * S::B + sl] = msum;
     __syncthreads();
     StagedInputs st;
-    if (next_o >= 0) stage_load<PREC>(st, g, next_o);
+    if (next_o >= 0) stage_load<PREC, NW>(st, g, next_o);
 
     // ---- variance contraction on the matrix cores
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NP = g.NT >> 1;
-    const int rounds = (NP + 3) >> 2;
+    const int rounds = (NP + NW - 1) / NW;
     int npairs = rounds;
-    if (wave_pair(w, rounds - 1) >= NP) npairs = rounds - 1;
+    if (rounds > 0 && wave_pair<NW>(w, rounds - 1) >= NP) npairs = rounds - 1;
     int nit = 0;
-    for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair(w, i) + 2;   // even
+    for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair<NW>(w, i) + 2;   // even
     const int r0 = (rotate && npairs > 0) ? (int)((unsigned)blk % (unsigned)npairs) : 0;
 
     const unsigned char *kgrp[G];
@@ -369,14 +377,14 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     }
     Cursor pc, mc;   // prefetch and compute cursors
     if (nit > 0) {
-        cursor_start(pc, w, npairs, r0, rev);
-        cursor_start(mc, w, npairs, r0, rev);
+        cursor_start<NW>(pc, w, npairs, r0, rev);
+        cursor_start<NW>(mc, w, npairs, r0, rev);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int b0 = pair_block(pc);
             load_wblock<PREC>(ring[r][0], g, o, b0, lane);
             load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-            cursor_next(pc, w, npairs, r0, rev);
+            cursor_next<NW>(pc, w, npairs, r0, rev);
         }
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
@@ -389,12 +397,12 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                 const int b0 = pair_block(pc);
                 load_wblock<PREC>(ring[r][0], g, o, b0, lane);
                 load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-                cursor_next(pc, w, npairs, r0, rev);
+                cursor_next<NW>(pc, w, npairs, r0, rev);
             }
             KOp<PREC> kuse[G];
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) kuse[gg] = kcur[gg];
-            const bool pair_end = cursor_next(mc, w, npairs, r0, rev);
+            const bool pair_end = cursor_next<NW>(mc, w, npairs, r0, rev);
             if (base + r + 1 < nit) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
@@ -424,10 +432,10 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
     }
     __syncthreads();
-    if (next_o >= 0) stage_store<PREC>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
+    if (next_o >= 0) stage_store<PREC, NW>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
     float v2 = 0.0f, m = 0.0f;
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) v2 += vred[ww * S::B + sl];
+    for (int ww = 0; ww < NW; ++ww) v2 += vred[ww * S::B + sl];
 #pragma unroll
     for (int p = 0; p < S::parts; ++p) m += pred[p * S::B + sl];
     var_out = g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));

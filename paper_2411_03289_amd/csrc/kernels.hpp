@@ -92,7 +92,8 @@ struct UpdateArgs {
 size_t rollout_lds_bytes(int precision, int G, int Mpad);
 // largest sample-group count whose LDS plan fits a compute unit (1 or 2)
 int rollout_groups(int precision, int Mpad);
-hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, hipStream_t st);
+// G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8).
+hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, hipStream_t st);
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
                                 int precision, int G, int Mpad_max, int grid, hipStream_t st);
 hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st);

@@ -28,10 +28,10 @@ namespace gpmppi {
 
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
 // problem; called by all threads of a workgroup.
-template <int PREC, int G>
+template <int PREC, int G, int NW = kWaves>
 __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, unsigned char *lds, float *pred,
                                               float *ored, float *vred) {
-    using S = Shapes<PREC, G>;
+    using S = Shapes<PREC, G, NW>;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int sl = lane % S::B;                     // sample within the block
@@ -76,8 +76,8 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 
     {   // inputs of output 0 (the first output of step 0)
         StagedInputs st;
-        stage_load<PREC>(st, a.gp, 0);
-        stage_store<PREC>(st, a.gp, lds, zs_off);
+        stage_load<PREC, NW>(st, a.gp, 0);
+        stage_store<PREC, NW>(st, a.gp, lds, zs_off);
     }
     for (int k = 0; k < a.T; ++k) {
         // even steps: outputs 0 then 1; odd steps: 1 then 0 (and blocks reversed)
@@ -91,7 +91,7 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
             __syncthreads();   // staged inputs visible; previous k-operand readers are done
             const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
                                  q[3] * a.gp.scale[o][3]};
-            gp_output<PREC, G>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
+            gp_output<PREC, G, NW>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
                                m[o], s2[o]);
         }
 
@@ -244,14 +244,14 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
     if (writer) a.costs[sg] = S_;
 }
 
-template <int PREC, int G>
-__global__ __launch_bounds__(kThreads) void rollout_kernel(RolloutArgs a) {
-    using S = Shapes<PREC, G>;
+template <int PREC, int G, int NW>
+__global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
+    using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::parts * S::B];
     __shared__ float ored[S::parts * S::B];
-    __shared__ float vred[kWaves * S::B];
-    rollout_block<PREC, G>(a, blockIdx.x, lds, pred, ored, vred);
+    __shared__ float vred[NW * S::B];
+    rollout_block<PREC, G, NW>(a, blockIdx.x, lds, pred, ored, vred);
 }
 
 // Persistent rollout of many independent problems: every workgroup takes
@@ -342,14 +342,20 @@ static hipError_t set_lds(F *fn, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int PREC, int G>
+template <int PREC, int G, int NW>
 static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
     const size_t lds = dyn_lds_bytes<PREC, G>(a.gp.Mpad);
-    hipError_t e = set_lds(rollout_kernel<PREC, G>, lds);
+    hipError_t e = set_lds(rollout_kernel<PREC, G, NW>, lds);
     if (e != hipSuccess) return e;
     const dim3 grid((a.K + 32 * G - 1) / (32 * G));
-    hipLaunchKernelGGL((rollout_kernel<PREC, G>), grid, dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((rollout_kernel<PREC, G, NW>), grid, dim3(64 * NW), lds, st, a);
     return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_rollout_p(const RolloutArgs &a, int G, int NW, hipStream_t st) {
+    if (NW == 8) return G == 2 ? launch_rollout_t<PREC, 2, 8>(a, st) : launch_rollout_t<PREC, 1, 8>(a, st);
+    return G == 2 ? launch_rollout_t<PREC, 2, kWaves>(a, st) : launch_rollout_t<PREC, 1, kWaves>(a, st);
 }
 
 template <int PREC, int G>
@@ -381,12 +387,12 @@ hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d,
     }
 }
 
-hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, hipStream_t st) {
-    if (G < 1 || G > groups_for(precision, a.gp.Mpad)) return hipErrorInvalidValue;
+hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, a.gp.Mpad) || (NW != kWaves && NW != 8)) return hipErrorInvalidValue;
     switch (precision) {
-        case GPMPPI_FP32: return G == 2 ? launch_rollout_t<GPMPPI_FP32, 2>(a, st) : launch_rollout_t<GPMPPI_FP32, 1>(a, st);
-        case GPMPPI_BF16: return G == 2 ? launch_rollout_t<GPMPPI_BF16, 2>(a, st) : launch_rollout_t<GPMPPI_BF16, 1>(a, st);
-        default: return G == 2 ? launch_rollout_t<GPMPPI_BF16X3, 2>(a, st) : launch_rollout_t<GPMPPI_BF16X3, 1>(a, st);
+        case GPMPPI_FP32: return launch_rollout_p<GPMPPI_FP32>(a, G, NW, st);
+        case GPMPPI_BF16: return launch_rollout_p<GPMPPI_BF16>(a, G, NW, st);
+        default: return launch_rollout_p<GPMPPI_BF16X3>(a, G, NW, st);
     }
 }
 

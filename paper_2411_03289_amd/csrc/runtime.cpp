@@ -84,6 +84,7 @@ struct gpmppi_ctx {
     // device buffers
     float *zs = nullptr, *alpha = nullptr, *zs2 = nullptr, *cza = nullptr;
     int groups = 1;                  // sample groups of 32 per rollout workgroup (tuned)
+    int waves = 4;                   // wave64s per rollout workgroup, 4 or 8 (tuned)
     int rotate = 1;                  // block-dependent start of the walk over W (tuned)
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
@@ -286,7 +287,7 @@ const float *enqueue_tightening(gpmppi_ctx *c, const float *x0, const float *U, 
     n.noise.sig_v = 0.0f;
     n.noise.sig_w = 0.0f;
     n.trace.sxy_d = c->tight;
-    err = launch_rollout(n, c->params.precision, c->groups, st);
+    err = launch_rollout(n, c->params.precision, c->groups, c->waves, st);
     return c->tight;
 }
 
@@ -537,7 +538,7 @@ gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d,
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, (hipStream_t)stream));
     return GPMPPI_OK;
 }
 
@@ -559,7 +560,7 @@ gpmppi_status gpmppi_step(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, (hipStream_t)stream));
     const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
     HIP_TRY(launch_update(u, (hipStream_t)stream));
     return GPMPPI_OK;
@@ -603,7 +604,7 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t
         HIP_TRY(e);
         RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
         a.tight_sxy = tight;
-        HIP_TRY(launch_rollout(a, c->params.precision, c->groups, s));
+        HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, s));
         const UpdateArgs u = update_args(c, c->cost_scratch, U_d, seed0, U_d, nullptr, counter);
         HIP_TRY(launch_update(u, s));
         HIP_TRY(launch_plant_shift(x_d, x_d, U_d, c->params.T, c->dyn, (float)amplitude, counter, x_hist_d,
@@ -714,6 +715,8 @@ int wg_capacity(int precision, int G, int Mpad) {
 
 gpmppi_status check_tuning(const gpmppi_tuning *t, int G_max, int wg_max, bool batch) {
     if (!t) return fail(GPMPPI_E_INVALID, "tuning is NULL");
+    if (batch ? t->waves != 4 : (t->waves != 4 && t->waves != 8))
+        return fail(GPMPPI_E_INVALID, "waves must be 4%s (got %d)", batch ? " for batches" : " or 8", t->waves);
     if (t->groups < 1 || t->groups > G_max)
         return fail(GPMPPI_E_INVALID, "groups must lie in [1, %d] here (got %d)", G_max, t->groups);
     if (t->rotate != 0 && t->rotate != 1) return fail(GPMPPI_E_INVALID, "rotate must be 0 or 1");
@@ -783,13 +786,14 @@ gpmppi_status gpmppi_set_tuning(gpmppi_ctx *c, const gpmppi_tuning *t) {
     if (st != GPMPPI_OK) return st;
     c->groups = t->groups;
     c->rotate = t->rotate;
+    c->waves = t->waves;
     return GPMPPI_OK;
 }
 
 gpmppi_status gpmppi_get_tuning(const gpmppi_ctx *c, gpmppi_tuning *t) {
     g_last_error.clear();
     if (!c || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
-    *t = gpmppi_tuning{c->groups, c->rotate, 1, 0, 0.0};
+    *t = gpmppi_tuning{c->groups, c->rotate, 1, 0, c->waves, 0.0};
     return GPMPPI_OK;
 }
 
@@ -800,12 +804,14 @@ gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
     hipStream_t st = (hipStream_t)stream;
     const int G_max = rollout_groups(c->params.precision, c->Mpad);
-    const int keep_groups = c->groups, keep_rotate = c->rotate;
-    gpmppi_tuning best{c->groups, c->rotate, 1, 0, -1.0};
+    const int keep_groups = c->groups, keep_rotate = c->rotate, keep_waves = c->waves;
+    gpmppi_tuning best{c->groups, c->rotate, 1, 0, c->waves, -1.0};
     for (int G = 1; G <= G_max; ++G)
-        for (int rot = 0; rot <= 1; ++rot) {
+        for (int rot = 0; rot <= 1; ++rot)
+        for (int nw = 4; nw <= 8; nw += 4) {
             c->groups = G;
             c->rotate = rot;
+            c->waves = nw;
             double ms = 0.0;
             gpmppi_status r = time_launches(
                 [&]() { return gpmppi_rollout(c, x0_d, U_d, seed, c->cost_scratch, nullptr, stream); }, reps, st,
@@ -813,12 +819,14 @@ gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
             if (r != GPMPPI_OK) {
                 c->groups = keep_groups;
                 c->rotate = keep_rotate;
+                c->waves = keep_waves;
                 return r;
             }
-            if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, ms};
+            if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, nw, ms};
         }
     c->groups = best.groups;
     c->rotate = best.rotate;
+    c->waves = best.waves;
     if (chosen) *chosen = best;
     return GPMPPI_OK;
 }
@@ -919,7 +927,7 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
     (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     b->cus = std::max(1, b->cus);
     b->wg_per_cu_max = wg_capacity(b->precision, b->G_max, b->Mpad_max);
-    if ((st = batch_install(b, gpmppi_tuning{b->G_max, 1, b->wg_per_cu_max, 0, 0.0})) != GPMPPI_OK) {
+    if ((st = batch_install(b, gpmppi_tuning{b->G_max, 1, b->wg_per_cu_max, 0, 4, 0.0})) != GPMPPI_OK) {
         delete b;
         return st;
     }
@@ -938,7 +946,7 @@ gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t) {
 gpmppi_status gpmppi_batch_get_tuning(const gpmppi_batch *b, gpmppi_tuning *t) {
     g_last_error.clear();
     if (!b || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
-    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, 0.0};
+    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, 4, 0.0};
     return GPMPPI_OK;
 }
 
@@ -948,14 +956,14 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
     if (!b || !x0_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
     if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
     hipStream_t st = (hipStream_t)stream;
-    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, 0.0};
-    gpmppi_tuning best{0, 0, 0, 0, -1.0};
+    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, 4, 0.0};
+    gpmppi_tuning best{0, 0, 0, 0, 4, -1.0};
     for (int G = 1; G <= b->G_max; ++G) {
         const int wmax = wg_capacity(b->precision, G, b->Mpad_max);
         for (int rot = 0; rot <= 1; ++rot)
             for (int w = 1; w <= wmax; ++w)
                 for (int ord = 0; ord <= 1; ++ord) {
-                    const gpmppi_tuning cand{G, rot, w, ord, 0.0};
+                    const gpmppi_tuning cand{G, rot, w, ord, 4, 0.0};
                     gpmppi_status r = batch_install(b, cand);
                     double ms = 0.0;
                     if (r == GPMPPI_OK) {
@@ -975,7 +983,7 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
                         (void)batch_install(b, keep);
                         return r;
                     }
-                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, ms};
+                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, 4, ms};
                 }
     }
     gpmppi_status r = batch_install(b, best);

@@ -374,16 +374,19 @@ def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
     ctx = B.gpmppi_init(pr, B.FP32)
     for groups in (1, 2):
         for rotate in (0, 1):
-            B.gpmppi_set_tuning(ctx, groups, rotate)
-            assert B.gpmppi_get_tuning(ctx)["groups"] == groups
-            S_g, tr_g = gpu_rollout(pr, ctx=ctx)
-            _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"shape groups={groups} rotate={rotate}")
-            S_g2, _ = gpu_rollout(pr, ctx=ctx)
-            np.testing.assert_array_equal(S_g, S_g2)
+            for waves in (4, 8):
+                B.gpmppi_set_tuning(ctx, groups, rotate, waves)
+                got = B.gpmppi_get_tuning(ctx)
+                assert (got["groups"], got["waves"]) == (groups, waves)
+                S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+                _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"shape groups={groups} rotate={rotate} waves={waves}")
+                S_g2, _ = gpu_rollout(pr, ctx=ctx)
+                np.testing.assert_array_equal(S_g, S_g2)
     chosen = B.gpmppi_tune(ctx, dev(pr.x0), dev(pr.U0), pr.seed, reps=2)
     print("tuning", chosen, flush=True)
     got = B.gpmppi_get_tuning(ctx)
-    assert (got["groups"], got["rotate"]) == (chosen["groups"], chosen["rotate"]) and chosen["ms"] > 0
-    for bad in ((0, 1), (3, 0), (1, 5)):
+    assert (got["groups"], got["rotate"], got["waves"]) == (chosen["groups"], chosen["rotate"], chosen["waves"])
+    assert chosen["ms"] > 0
+    for bad in ((0, 1, 4), (3, 0, 4), (1, 5, 4), (1, 1, 6)):
         with pytest.raises(B.GpmppiError):
             B.gpmppi_set_tuning(ctx, *bad)
