@@ -71,6 +71,87 @@ def cpu_baseline(pr, n_samples):
                       f"FP64 NumPy/SciPy, {dt:.1f} s wall"}
 
 
+def extras(B, W, torch, log_fn):
+    """Informational timings of the other workloads (not the reported value):
+    c1 closed loop (K=4096, T=50, M=256, 100 steps, HIP graph), c3 batch (64
+    problems of uneven shape, 50 closed-loop steps in one persistent launch per
+    step, HIP graph, tuned), c4 gradient (K=4096, T=50, M=512, tau 0.05 m,
+    checkpoints every 10 steps)."""
+    import numpy as np
+    out = {}
+    f32 = dict(device="cuda", dtype=torch.float32)
+    ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
+    stream = torch.cuda.current_stream()
+    try:   # c1 closed loop
+        pr = W.make_config(1)
+        ctx = B.gpmppi_init(pr, B.FP32)
+        B.gpmppi_tune(ctx, torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32), pr.seed, 2, stream)
+        x, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
+        B.gpmppi_closed_loop(ctx, x, U, pr.seed, 5, 0.3, use_graph=True, stream=stream)   # warm-up
+        x, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        B.gpmppi_closed_loop(ctx, x, U, pr.seed, 100, 0.3, use_graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 100
+        out["c1_closed_loop"] = {"ms_per_control_step": ms, "sample_steps_per_s": pr.K * pr.T / (ms * 1e-3),
+                                 "workload": "K=4096 T=50 M=256 20 obstacles figure-eight, 100 steps, HIP graph"}
+        log_fn(f"[bench] extra c1 closed loop {ms:.3f} ms/step")
+        del ctx
+    except Exception as exc:   # informational only
+        out["c1_closed_loop"] = {"error": repr(exc)}
+    try:   # c3 batch
+        probs = [W.make_batch_problem(p) for p in range(64)]
+        b = B.gpmppi_batch_init(probs, B.FP32)
+        U_off, K_off = B.gpmppi_batch_layout(b)
+        x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), **f32)
+        U0 = torch.tensor(np.concatenate([p.U0.reshape(-1) for p in probs]), **f32)
+        shape = B.gpmppi_batch_tune(b, x0, U0, probs[0].seed, 1, stream)
+        x, U = x0.clone(), U0.clone()
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 2, 0.3, use_graph=True, stream=stream)   # warm-up
+        x, U = x0.clone(), U0.clone()
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 50, 0.3, use_graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        ss = sum(p.K * p.T for p in probs)
+        out["c3_batch"] = {"ms_per_control_step": ms, "sample_steps_per_s": ss / (ms * 1e-3),
+                           "sample_steps_per_control_step": ss, "shape": shape,
+                           "workload": "64 problems, K in {1024..16384}, T in [30, 100], M in {64..1024}, "
+                                       "0-50 obstacles, 50 closed-loop steps, HIP graph"}
+        log_fn(f"[bench] extra c3 batch {ms:.3f} ms/step")
+        del b
+    except Exception as exc:
+        out["c3_batch"] = {"error": repr(exc)}
+    try:   # c4 gradient
+        pr = W.make_config(4)
+        ctx = B.gpmppi_init(pr, B.FP32)
+        x0, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
+        J, dU = torch.empty(1, **f32), torch.empty_like(U)
+        dle, dls = torch.empty((2, 4), **f32), torch.empty(2, **f32)
+        B.gpmppi_grad(ctx, x0, U, pr.seed, 0.05, 10, J, dU, dle, dls, stream=stream)   # warm-up + workspace
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            B.gpmppi_grad(ctx, x0, U, pr.seed, 0.05, 10, J, dU, dle, dls, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        out["c4_grad"] = {"ms_per_gradient": ms, "sample_steps_per_s": pr.K * pr.T / (ms * 1e-3),
+                          "workload": "K=4096 T=50 M=512 20 obstacles figure-eight, tau 0.05 m, checkpoints every 10"}
+        log_fn(f"[bench] extra c4 gradient {ms:.3f} ms")
+        del ctx
+    except Exception as exc:
+        out["c4_grad"] = {"error": repr(exc)}
+    return out
+
+
 def measured_traffic(form):
     import hashlib
     h = hashlib.sha256()
@@ -93,6 +174,7 @@ def main():
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the informational c1 / c3 / c4 timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path is single-GPU (multi-GPU sharding is design only); "
@@ -190,6 +272,8 @@ def main():
         "speedup_vs_fp32": {n: results["fp32"]["ms_per_step"] / results[n]["ms_per_step"]
                             for n in results if "fp32" in results},
     }
+    if not args.no_extras:
+        line["extras"] = extras(B, W, torch, log)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_samples} samples")
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_samples)

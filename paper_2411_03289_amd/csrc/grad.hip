@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     __shared__ float vred[kWaves * kB];
     __shared__ float vb[kParts * kB], vo[kParts * kB];
     __shared__ int ib[kParts * kB], io[kParts * kB];
-    __shared__ float gred[9 * kParts * kB];
+    __shared__ __align__(16) float gred[9 * kParts * kB];
     __shared__ float mb_s[2][kB], sb_s[2][kB], ub_s[2][kB];
 
     const int tid = threadIdx.x;
@@ -220,9 +220,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     NoiseParams np = a.noise;
 
     // per-sample accumulators of the hyperparameter terms through k (o, theta)
-    float hyp[2][5] = {};
+    double hyp[2][5] = {};
     // this thread's share of b = sum mbar r (points j = tid + 256 i)
-    float bacc[2][2] = {};
+    double bacc[2][2] = {};
 
     const int nseg = (T + C - 1) / C;
     float X = 0, Y = 0, th = 0, v = 0, w_ = 0;
@@ -413,12 +413,12 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                 for (int jj = 0; jj < 2; ++jj) {
                     const int j = tid + kThreads * jj;
                     if (j < Mpad) {
-                        float acc = bacc[o][jj];
+                        double acc = bacc[o][jj];
                         float *Rrow = a.R + ((size_t)o * T * K + (size_t)k * K + (size_t)blk * kB) * Mpad + j;
                         for (int s = 0; s < kB; ++s) {
                             if (blk * kB + s < K) {
                                 const float rv = rb[s * (Mpad + 1) + j];
-                                acc = fmaf(mb_s[o][s], rv, acc);
+                                acc += (double)(mb_s[o][s] * rv);
                                 Rrow[(size_t)s * Mpad] = rv;
                             }
                         }
@@ -438,9 +438,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     qb[d] += 2.0f * kLn2 * g.scale[o][d] * tot[1 + d];
-                    hyp[o][d] += -2.0f * kLn2 * tot[5 + d];
+                    hyp[o][d] += (double)(-2.0f * kLn2 * tot[5 + d]);
                 }
-                hyp[o][4] += -2.0f * tot[0] + 2.0f * g.sf2[o] * sbo;
+                hyp[o][4] += (double)(-2.0f * tot[0] + 2.0f * g.sf2[o] * sbo);
             }
             vbk += qb[0];
             wbk += qb[1];
@@ -470,16 +470,17 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     (void)np;
     // ---- per-workgroup partial sums
     __syncthreads();
+    double *hred = reinterpret_cast<double *>(gred);   // 10 x 32 doubles
     if (writer) {
 #pragma unroll
         for (int o = 0; o < 2; ++o)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) gred[(o * 5 + i) * kB + sl] = valid ? hyp[o][i] : 0.0f;
+            for (int i = 0; i < 5; ++i) hred[(o * 5 + i) * kB + sl] = valid ? hyp[o][i] : 0.0;
     }
     __syncthreads();
     if (tid < 10) {
-        float s = 0.0f;
-        for (int i = 0; i < kB; ++i) s += gred[tid * kB + i];
+        double s = 0.0;
+        for (int i = 0; i < kB; ++i) s += hred[tid * kB + i];
         a.hpart[(size_t)blk * 10 + tid] = s;
     }
     for (int o = 0; o < 2; ++o)
@@ -493,22 +494,22 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 // dA_ij / dtheta contracted with a weight c_ij, theta = (log ell_0..3, log sf):
 // K_ij = exp2(c2 - |zs_i - zs_j|^2); dA/dlog ell_d = K 2 ln2 (zs_id - zs_jd)^2,
 // dA/dlog sf = 2 K (the sn^2 I part does not depend on them).
-__device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const float4 &zj, float c2, float acc[5]) {
+__device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const float4 &zj, float c2, double acc[5]) {
     const float d0 = zi.x - zj.x, d1 = zi.y - zj.y, d2 = zi.z - zj.z, d3 = zi.w - zj.w;
     const float e0 = d0 * d0, e1 = d1 * d1, e2 = d2 * d2, e3 = d3 * d3;
     const float Kij = __builtin_amdgcn_exp2f(c2 - (e0 + e1 + e2 + e3));
     const float ck = cval * Kij;
     const float c2l = 2.0f * kLn2 * ck;
-    acc[0] = fmaf(c2l, e0, acc[0]);
-    acc[1] = fmaf(c2l, e1, acc[1]);
-    acc[2] = fmaf(c2l, e2, acc[2]);
-    acc[3] = fmaf(c2l, e3, acc[3]);
-    acc[4] = fmaf(2.0f, ck, acc[4]);
+    acc[0] += (double)(c2l * e0);
+    acc[1] += (double)(c2l * e1);
+    acc[2] += (double)(c2l * e2);
+    acc[3] += (double)(c2l * e3);
+    acc[4] += (double)(2.0f * ck);
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
+__device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += shfl_xor(x, m);
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
     return x;
 }
 
@@ -518,8 +519,8 @@ __device__ __forceinline__ float wave_sum(float x) {
 // 32 x 32 tiles (2 (w >> 1) + {0, 1}, 2 (w & 1) + {0, 1}) of the block.
 __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, const float *Gw, long long TK, int Mpad,
                                                              const float *zs, float c20, float c21, int nsplit,
-                                                             float *ppart) {
-    __shared__ float red[kWaves][5];
+                                                             double *ppart) {
+    __shared__ double red[kWaves][5];
     const int pair = blockIdx.x, split = blockIdx.y, o = blockIdx.z;
     const int npairs = gridDim.x;
     const int nb = (Mpad + 127) / 128;
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, con
     const float c2 = o ? c21 : c20;
     const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
     const float weight = bi == bj ? 1.0f : 2.0f;
-    float cacc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -580,43 +581,44 @@ __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, con
         }
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
-        const float v = wave_sum(cacc[t]);
+        const double v = wave_sum(cacc[t]);
         if (lane == 0) red[w][t] = v;
     }
     __syncthreads();
     if (threadIdx.x < 5) {
-        const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
         ppart[((size_t)(o * npairs + pair) * nsplit + split) * 5 + threadIdx.x] = v;
     }
 }
 
 // b = sum over workgroups of the partial b, then sum_ij b_i alpha_j dA_ij/dtheta:
 // one thread per row i; bterm[(o * gridDim.x + block) * 5 + theta].
-__global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const float *bpart, int nwg, int Mpad, const float *zs,
+__global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const double *bpart, int nwg, int Mpad, const float *zs,
                                                               const float *alpha, float c20, float c21,
-                                                              float *bterm) {
-    __shared__ float red[kWaves][5];
+                                                              double *bterm) {
+    __shared__ double red[kWaves][5];
     const int o = blockIdx.y;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const float c2 = o ? c21 : c20;
     const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
     const float *al = alpha + (size_t)o * Mpad;
-    float cacc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < Mpad) {
-        float b = 0.0f;
+        double b = 0.0;
         for (int wg = 0; wg < nwg; ++wg) b += bpart[((size_t)wg * 2 + o) * Mpad + i];
         const float4 zi = z[i];
-        for (int j = 0; j < Mpad; ++j) dA_contract(b * al[j], zi, z[j], c2, cacc);
+        const float bf = (float)b;
+        for (int j = 0; j < Mpad; ++j) dA_contract(bf * al[j], zi, z[j], c2, cacc);
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
-        const float v = wave_sum(cacc[t]);
+        const double v = wave_sum(cacc[t]);
         if (lane == 0) red[w][t] = v;
     }
     __syncthreads();
     if (threadIdx.x < 5) {
-        const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
         bterm[((size_t)o * gridDim.x + blockIdx.x) * 5 + threadIdx.x] = v;
     }
 }
@@ -624,8 +626,8 @@ __global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const float *bpart
 // Fixed-order final sums: J = mean smoothed cost, dU[k][c], and the
 // hyperparameter gradient = direct (through k) + (P - b alpha^T) : dA/dtheta.
 __global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs, int K, int T, int nwg,
-                                                              const float *upart, const float *hpart,
-                                                              const float *ppart, int nppart, const float *bterm,
+                                                              const float *upart, const double *hpart,
+                                                              const double *ppart, int nppart, const double *bterm,
                                                               int nbterm, float *J, float *dU, float *dlog_ell,
                                                               float *dlog_sf) {
     __shared__ float red[kThreads];
@@ -640,17 +642,17 @@ __global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs
     }
     if (tid == 0) J[0] = red[0] / (float)K;
     for (int kc = tid; kc < 2 * T; kc += kThreads) {
-        float v = 0.0f;
+        double v = 0.0;
         for (int wg = 0; wg < nwg; ++wg) v += upart[(size_t)wg * 2 * T + kc];
-        dU[kc] = v;
+        dU[kc] = (float)v;
     }
     if (tid < 10) {
         const int o = tid / 5, t = tid % 5;
-        float direct = 0.0f, mat = 0.0f, bt = 0.0f;
+        double direct = 0.0, mat = 0.0, bt = 0.0;
         for (int wg = 0; wg < nwg; ++wg) direct += hpart[(size_t)wg * 10 + tid];
         for (int i = 0; i < nppart; ++i) mat += ppart[((size_t)o * nppart + i) * 5 + t];
         for (int i = 0; i < nbterm; ++i) bt += bterm[((size_t)o * nbterm + i) * 5 + t];
-        const float g = direct + mat - bt;
+        const float g = (float)(direct + mat - bt);
         if (t < 4) dlog_ell[o * 4 + t] = g;
         else dlog_sf[o] = g;
     }

@@ -163,8 +163,8 @@ struct GradArgs {
     float *seg;              // [nwg][C + 1][28][32] per-workgroup segment scratch
     float *R;                // [2][T K][Mpad]
     float *Gw;               // [2][T K]
-    float *bpart;            // [nwg][2][Mpad]
-    float *hpart;            // [nwg][10]
+    double *bpart;           // [nwg][2][Mpad]
+    double *hpart;           // [nwg][10]
     float *upart;            // [nwg][T][2]
 };
 
@@ -172,7 +172,7 @@ struct GradLaunch {
     int nwg;                 // grad_kernel workgroups = ceil(K / 32)
     int npairs, nsplit;      // grad_syrk_kernel grid: 128-blocks (bi <= bj) x row splits
     int nbterm;              // grad_bterm_kernel blocks per output
-    float *ppart, *bterm;    // partial contractions
+    double *ppart, *bterm;   // partial contractions
     float *J, *dU, *dlog_ell, *dlog_sf;   // outputs
 };
 // Dynamic LDS of grad_kernel at this Mpad (must be <= 160 KB minus its static LDS).

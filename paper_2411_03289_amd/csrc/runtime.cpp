@@ -1104,9 +1104,9 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
         return at;
     };
     const size_t o_ck = take((size_t)nck * 20 * K), o_seg = take((size_t)l.nwg * (C + 1) * 28 * 32),
-                 o_R = take((size_t)2 * TK * Mpad), o_G = take((size_t)2 * TK), o_b = take((size_t)l.nwg * 2 * Mpad),
-                 o_h = take((size_t)l.nwg * 10), o_u = take((size_t)l.nwg * T * 2),
-                 o_p = take((size_t)2 * l.npairs * l.nsplit * 5), o_bt = take((size_t)2 * l.nbterm * 5),
+                 o_R = take((size_t)2 * TK * Mpad), o_G = take((size_t)2 * TK), o_b = take((size_t)l.nwg * 2 * Mpad * 2),
+                 o_h = take((size_t)l.nwg * 10 * 2), o_u = take((size_t)l.nwg * T * 2),
+                 o_p = take((size_t)2 * l.npairs * l.nsplit * 5 * 2), o_bt = take((size_t)2 * l.nbterm * 5 * 2),
                  o_c = take((size_t)K);
     if (off > c->grad_ws_bytes) {
         if (c->grad_ws) (void)hipFree(c->grad_ws);
@@ -1142,11 +1142,11 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     a.seg = reinterpret_cast<float *>(ws + o_seg);
     a.R = reinterpret_cast<float *>(ws + o_R);
     a.Gw = reinterpret_cast<float *>(ws + o_G);
-    a.bpart = reinterpret_cast<float *>(ws + o_b);
-    a.hpart = reinterpret_cast<float *>(ws + o_h);
+    a.bpart = reinterpret_cast<double *>(ws + o_b);
+    a.hpart = reinterpret_cast<double *>(ws + o_h);
     a.upart = reinterpret_cast<float *>(ws + o_u);
-    l.ppart = reinterpret_cast<float *>(ws + o_p);
-    l.bterm = reinterpret_cast<float *>(ws + o_bt);
+    l.ppart = reinterpret_cast<double *>(ws + o_p);
+    l.bterm = reinterpret_cast<double *>(ws + o_bt);
     l.J = J_d;
     l.dU = dU_d;
     l.dlog_ell = dlog_ell_d;
