@@ -127,6 +127,37 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
     }
 }
 
+// The products of a pair's first iteration, accumulated onto zero.
+template <int PREC>
+__device__ __forceinline__ v16f mma_first(const WBlock<PREC> &b, const KOp<PREC> &k) {
+    v16f acc;
+    if constexpr (PREC == GPMPPI_FP32) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].x, k.v[0].x, v16f{}, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].y, k.v[0].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].z, k.v[0].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].w, k.v[0].w, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].x, k.v[q].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].y, k.v[q].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].z, k.v[q].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].w, k.v[q].w, acc, 0, 0, 0);
+        }
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[0]), as_bf(k.h[0]), v16f{}, 0, 0, 0);
+        if constexpr (PREC == GPMPPI_BF16X3) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[0]), as_bf(k.l[0]), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[0]), as_bf(k.h[0]), acc, 0, 0, 0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[1]), as_bf(k.h[1]), acc, 0, 0, 0);
+        if constexpr (PREC == GPMPPI_BF16X3) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[1]), as_bf(k.l[1]), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[1]), as_bf(k.h[1]), acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
 // Pair list of wave w of NW: round i holds pairs NW i .. NW i + NW - 1,
 // assigned in snake order so that the summed pair lengths (2u + 2) balance
 // across waves.
@@ -300,8 +331,9 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
             K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
         }
     } else {
-        // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs); its FP32 rounding
-        // (~1e-6 relative in k) is far below the BF16 operand rounding (2^-9)
+        // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs) = c2 - |q - zs|^2 <= c2 up to
+        // rounding, so exp2 needs no clamp; its FP32 rounding (~1e-6 relative in k)
+        // is far below the BF16 operand rounding (2^-9)
         const float4 *cza = zs + Mpad;   // (c2 - |zs|^2, alpha) pairs
         const float qq = qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3];
         for (int c = part; c < nchunk; c += S::parts) {
@@ -322,7 +354,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                     acc = fmaf(qs[1], z2.y, acc);
                     acc = fmaf(qs[2], z2.z, acc);
                     acc = fmaf(qs[3], z2.w, acc);
-                    kv[e] = __builtin_amdgcn_exp2f(fminf(acc, 64.0f));
+                    kv[e] = __builtin_amdgcn_exp2f(acc);
                 }
             }
 #pragma unroll
@@ -364,9 +396,10 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     const unsigned char *kgrp[G];
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
-    // register ring of two iterations (two W blocks each); k operand one iteration ahead
+    // register ring of two iterations (two W blocks each); the k operand of
+    // iteration i sits in kb[i % 2], loaded one iteration ahead
     WBlock<PREC> ring[2][2];
-    KOp<PREC> kcur[G];
+    KOp<PREC> kb[2][G];
     v16f acc[2][G];
     float sq[G];
 #pragma unroll
@@ -375,6 +408,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         acc[1][gg] = v16f{};
         sq[gg] = 0.0f;
     }
+    bool pair_start = true;
     Cursor pc, mc;   // prefetch and compute cursors
     if (nit > 0) {
         cursor_start<NW>(pc, w, npairs, r0, rev);
@@ -387,31 +421,38 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
             cursor_next<NW>(pc, w, npairs, r0, rev);
         }
 #pragma unroll
-        for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
+        for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
     }
     for (int base = 0; base < nit; base += 2) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const WBlock<PREC> wa = ring[r][0], wb = ring[r][1];
+            // this iteration's products; a pair's first iteration starts from zero
+            if (pair_start) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+                    acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
+                    acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
+                }
+            } else {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+                    mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
+                    mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
+                }
+            }
+            // refill this ring slot two iterations ahead, the other k slot one ahead
             if (base + r + 2 < nit) {
                 const int b0 = pair_block(pc);
                 load_wblock<PREC>(ring[r][0], g, o, b0, lane);
                 load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
                 cursor_next<NW>(pc, w, npairs, r0, rev);
             }
-            KOp<PREC> kuse[G];
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) kuse[gg] = kcur[gg];
             const bool pair_end = cursor_next<NW>(mc, w, npairs, r0, rev);
             if (base + r + 1 < nit) {
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kcur[gg], kgrp[gg], mc.it, lane, Mpad);
+                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], mc.it, lane, Mpad);
             }
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                mma_block<PREC>(acc[0][gg], wa, kuse[gg]);
-                mma_block<PREC>(acc[1][gg], wb, kuse[gg]);
-            }
+            pair_start = pair_end;
             if (pair_end) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) {
@@ -420,8 +461,6 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                         sq[gg] = fmaf(acc[0][gg][e], acc[0][gg][e], sq[gg]);
                         sq[gg] = fmaf(acc[1][gg][e], acc[1][gg][e], sq[gg]);
                     }
-                    acc[0][gg] = v16f{};
-                    acc[1][gg] = v16f{};
                 }
             }
         }
