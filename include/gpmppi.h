@@ -246,7 +246,7 @@ typedef struct {
     int32_t rotate;      /* 1: each workgroup starts its walk over W at a block-dependent row-pair; 0: at pair 0 */
     int32_t wg_per_cu;   /* batches: persistent workgroups per compute unit, 1 or 2 (LDS permitting) */
     int32_t order;       /* batches: 0 = items longest first, 1 = problem order */
-    int32_t waves;       /* wave64s per rollout workgroup: 4 or 8 (batches: 4) */
+    int32_t waves;       /* wave64s per rollout workgroup: 4 or 8 */
     double ms;           /* tune: mean rollout time of this shape in ms; ignored by set */
 } gpmppi_tuning;
 
@@ -296,7 +296,7 @@ gpmppi_status gpmppi_batch_closed_loop(gpmppi_batch *b, float *x_d, float *U_d, 
                                        double amplitude, float *x_hist_d, int32_t use_graph, void *stream);
 
 /* Batch autotuner: as gpmppi_tune over the batch's persistent rollout
- * (groups x rotate x wg_per_cu x order), with x0_d [n][5] and packed U_d. */
+ * (groups x rotate x wg_per_cu x order x waves), with x0_d [n][5] and packed U_d. */
 gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
                                 gpmppi_tuning *chosen, void *stream);
 gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t);

@@ -95,7 +95,7 @@ int rollout_groups(int precision, int Mpad);
 // G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8).
 hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, hipStream_t st);
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
-                                int precision, int G, int Mpad_max, int grid, hipStream_t st);
+                                int precision, int G, int NW, int Mpad_max, int grid, hipStream_t st);
 hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st);
 hipError_t launch_plant_shift_batch(float *x, float *U, const long long *U_off, const int *T, const Dyn *dyn,
                                     float amplitude, const uint32_t *step_counter, float *x_hist, int n,

@@ -258,14 +258,14 @@ __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
 // (problem, sample block) items from a shared counter until the list (sorted
 // longest first) is exhausted.  Results do not depend on which workgroup
 // runs an item.  *counter must be 0 at launch.
-template <int PREC, int G>
-__global__ __launch_bounds__(kThreads) void rollout_batch_kernel(const RolloutArgs *probs, const int2 *items,
+template <int PREC, int G, int NW>
+__global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(const RolloutArgs *probs, const int2 *items,
                                                                  int n_items, uint32_t *counter) {
-    using S = Shapes<PREC, G>;
+    using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::parts * S::B];
     __shared__ float ored[S::parts * S::B];
-    __shared__ float vred[kWaves * S::B];
+    __shared__ float vred[NW * S::B];
     __shared__ int next_item;
     for (;;) {
         __syncthreads();   // every thread has read the previous item
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void rollout_batch_kernel(const RolloutAr
         const int2 pb = items[it];
         const int p = __builtin_amdgcn_readfirstlane(pb.x);
         const int b = __builtin_amdgcn_readfirstlane(pb.y);
-        rollout_block<PREC, G>(probs[p], b, lds, pred, ored, vred);
+        rollout_block<PREC, G, NW>(probs[p], b, lds, pred, ored, vred);
     }
 }
 
@@ -358,32 +358,41 @@ static hipError_t launch_rollout_p(const RolloutArgs &a, int G, int NW, hipStrea
     return G == 2 ? launch_rollout_t<PREC, 2, kWaves>(a, st) : launch_rollout_t<PREC, 1, kWaves>(a, st);
 }
 
-template <int PREC, int G>
+template <int PREC, int G, int NW>
 static hipError_t launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items, uint32_t *counter,
                                          int Mpad_max, int grid, hipStream_t st) {
     const size_t lds = dyn_lds_bytes<PREC, G>(Mpad_max);
-    hipError_t e = set_lds(rollout_batch_kernel<PREC, G>, lds);
+    hipError_t e = set_lds(rollout_batch_kernel<PREC, G, NW>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rollout_batch_kernel<PREC, G>), dim3(grid), dim3(kThreads), lds, st, probs, items, n_items,
+    hipLaunchKernelGGL((rollout_batch_kernel<PREC, G, NW>), dim3(grid), dim3(64 * NW), lds, st, probs, items, n_items,
                        counter);
     return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_rollout_batch_p(const RolloutArgs *probs, const int2 *items, int n_items, uint32_t *counter,
+                                         int G, int NW, int Mpad_max, int grid, hipStream_t st) {
+    if (NW == 8)
+        return G == 2 ? launch_rollout_batch_t<PREC, 2, 8>(probs, items, n_items, counter, Mpad_max, grid, st)
+                      : launch_rollout_batch_t<PREC, 1, 8>(probs, items, n_items, counter, Mpad_max, grid, st);
+    return G == 2 ? launch_rollout_batch_t<PREC, 2, kWaves>(probs, items, n_items, counter, Mpad_max, grid, st)
+                  : launch_rollout_batch_t<PREC, 1, kWaves>(probs, items, n_items, counter, Mpad_max, grid, st);
 }
 
 int rollout_groups(int precision, int Mpad) { return groups_for(precision, Mpad); }
 
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
-                                int precision, int G, int Mpad_max, int grid, hipStream_t st) {
-    if (G < 1 || G > groups_for(precision, Mpad_max) || grid < 1) return hipErrorInvalidValue;
+                                int precision, int G, int NW, int Mpad_max, int grid, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, Mpad_max) || grid < 1 || (NW != kWaves && NW != 8))
+        return hipErrorInvalidValue;
     switch (precision) {
         case GPMPPI_FP32:
-            return G == 2 ? launch_rollout_batch_t<GPMPPI_FP32, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
-                          : launch_rollout_batch_t<GPMPPI_FP32, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+            return launch_rollout_batch_p<GPMPPI_FP32>(probs_d, items_d, n_items, counter, G, NW, Mpad_max, grid, st);
         case GPMPPI_BF16:
-            return G == 2 ? launch_rollout_batch_t<GPMPPI_BF16, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
-                          : launch_rollout_batch_t<GPMPPI_BF16, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+            return launch_rollout_batch_p<GPMPPI_BF16>(probs_d, items_d, n_items, counter, G, NW, Mpad_max, grid, st);
         default:
-            return G == 2 ? launch_rollout_batch_t<GPMPPI_BF16X3, 2>(probs_d, items_d, n_items, counter, Mpad_max, grid, st)
-                          : launch_rollout_batch_t<GPMPPI_BF16X3, 1>(probs_d, items_d, n_items, counter, Mpad_max, grid, st);
+            return launch_rollout_batch_p<GPMPPI_BF16X3>(probs_d, items_d, n_items, counter, G, NW, Mpad_max, grid,
+                                                         st);
     }
 }
 

@@ -674,7 +674,7 @@ gpmppi_status gpmppi_info(const gpmppi_ctx *c, int32_t *M_pad, double *z_p, doub
 
 struct gpmppi_batch {
     int n = 0, precision = 0, Mpad_max = 0, grid = 0, cus = 1;
-    int G = 1, G_max = 1, rotate = 1, wg_per_cu = 1, wg_per_cu_max = 1, order = 0;
+    int G = 1, G_max = 1, rotate = 1, wg_per_cu = 1, wg_per_cu_max = 1, order = 0, waves = 4;
     std::vector<gpmppi_ctx *> ctx;
     std::vector<long long> U_off, K_off;   // n + 1 each
     std::vector<double> cost;              // estimated rollout cost of one sample block, per problem
@@ -701,8 +701,8 @@ namespace {
 
 gpmppi_status batch_enqueue_step(gpmppi_batch *b, hipStream_t st) {
     HIP_TRY(launch_counter_reset(b->counters, st));
-    HIP_TRY(launch_rollout_batch(b->ra, b->items, b->n_items, b->counters, b->precision, b->G, b->Mpad_max,
-                                 b->grid, st));
+    HIP_TRY(launch_rollout_batch(b->ra, b->items, b->n_items, b->counters, b->precision, b->G, b->waves,
+                                 b->Mpad_max, b->grid, st));
     HIP_TRY(launch_update_batch(b->ua, b->upd_items, b->n_upd, st));
     return GPMPPI_OK;
 }
@@ -715,8 +715,7 @@ int wg_capacity(int precision, int G, int Mpad) {
 
 gpmppi_status check_tuning(const gpmppi_tuning *t, int G_max, int wg_max, bool batch) {
     if (!t) return fail(GPMPPI_E_INVALID, "tuning is NULL");
-    if (batch ? t->waves != 4 : (t->waves != 4 && t->waves != 8))
-        return fail(GPMPPI_E_INVALID, "waves must be 4%s (got %d)", batch ? " for batches" : " or 8", t->waves);
+    if (t->waves != 4 && t->waves != 8) return fail(GPMPPI_E_INVALID, "waves must be 4 or 8 (got %d)", t->waves);
     if (t->groups < 1 || t->groups > G_max)
         return fail(GPMPPI_E_INVALID, "groups must lie in [1, %d] here (got %d)", G_max, t->groups);
     if (t->rotate != 0 && t->rotate != 1) return fail(GPMPPI_E_INVALID, "rotate must be 0 or 1");
@@ -749,6 +748,7 @@ gpmppi_status batch_install(gpmppi_batch *b, const gpmppi_tuning &t) {
     b->rotate = t.rotate;
     b->wg_per_cu = t.wg_per_cu;
     b->order = t.order;
+    b->waves = t.waves;
     b->grid = std::max(1, std::min(b->n_items, b->cus * t.wg_per_cu));
     return GPMPPI_OK;
 }
@@ -946,7 +946,7 @@ gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t) {
 gpmppi_status gpmppi_batch_get_tuning(const gpmppi_batch *b, gpmppi_tuning *t) {
     g_last_error.clear();
     if (!b || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
-    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, 4, 0.0};
+    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0.0};
     return GPMPPI_OK;
 }
 
@@ -956,14 +956,15 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
     if (!b || !x0_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
     if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
     hipStream_t st = (hipStream_t)stream;
-    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, 4, 0.0};
+    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0.0};
     gpmppi_tuning best{0, 0, 0, 0, 4, -1.0};
     for (int G = 1; G <= b->G_max; ++G) {
         const int wmax = wg_capacity(b->precision, G, b->Mpad_max);
         for (int rot = 0; rot <= 1; ++rot)
             for (int w = 1; w <= wmax; ++w)
-                for (int ord = 0; ord <= 1; ++ord) {
-                    const gpmppi_tuning cand{G, rot, w, ord, 4, 0.0};
+                for (int ord = 0; ord <= 1; ++ord)
+                for (int nw = 4; nw <= 8; nw += 4) {
+                    const gpmppi_tuning cand{G, rot, w, ord, nw, 0.0};
                     gpmppi_status r = batch_install(b, cand);
                     double ms = 0.0;
                     if (r == GPMPPI_OK) {
@@ -974,7 +975,8 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
                                 HIP_TRY(launch_batch_patch(b->ra, b->ua, b->n, q, st));
                                 HIP_TRY(launch_counter_reset(b->counters, st));
                                 HIP_TRY(launch_rollout_batch(b->ra, b->items, b->n_items, b->counters,
-                                                             b->precision, b->G, b->Mpad_max, b->grid, st));
+                                                             b->precision, b->G, b->waves, b->Mpad_max, b->grid,
+                                                             st));
                                 return GPMPPI_OK;
                             },
                             reps, st, ms);
@@ -983,7 +985,7 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
                         (void)batch_install(b, keep);
                         return r;
                     }
-                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, 4, ms};
+                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, nw, ms};
                 }
     }
     gpmppi_status r = batch_install(b, best);

@@ -534,8 +534,8 @@ def gpmppi_batch_tune(b: Batch, x0, U, seed: int, reps: int = 2, stream=None) ->
     return t.as_dict()
 
 
-def gpmppi_batch_set_tuning(b: Batch, groups: int, rotate: int, wg_per_cu: int, order: int):
-    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, 4, 0.0)
+def gpmppi_batch_set_tuning(b: Batch, groups: int, rotate: int, wg_per_cu: int, order: int, waves: int = 4):
+    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, waves, 0.0)
     _check(lib().gpmppi_batch_set_tuning(b.handle, ctypes.byref(t)))
 
 

@@ -108,15 +108,15 @@ def test_batch_autotuner_choice_keeps_results_of_the_matching_single_shape():
     chosen = B.gpmppi_batch_tune(b, dev(x0), dev(U), seed, reps=1)
     print("batch tuning", chosen, flush=True)
     assert chosen["groups"] in (1, 2) and chosen["rotate"] in (0, 1) and chosen["wg_per_cu"] in (1, 2)
-    assert chosen["order"] in (0, 1) and chosen["ms"] > 0
+    assert chosen["order"] in (0, 1) and chosen["waves"] in (4, 8) and chosen["ms"] > 0
     got = B.gpmppi_batch_get_tuning(b)
-    assert {k: got[k] for k in ("groups", "rotate", "wg_per_cu", "order")} == \
-        {k: chosen[k] for k in ("groups", "rotate", "wg_per_cu", "order")}
+    assert {k: got[k] for k in ("groups", "rotate", "wg_per_cu", "order", "waves")} == \
+        {k: chosen[k] for k in ("groups", "rotate", "wg_per_cu", "order", "waves")}
     # the schedule (order, occupancy) never changes a result; the shape (groups, rotate)
     # selects the same grouping of partial sums as a single context set to it
     outs = []
     for wg, order in ((1, 1), (chosen["wg_per_cu"], chosen["order"])):
-        B.gpmppi_batch_set_tuning(b, chosen["groups"], chosen["rotate"], wg, order)
+        B.gpmppi_batch_set_tuning(b, chosen["groups"], chosen["rotate"], wg, order, chosen["waves"])
         Uo = t.empty(U_off[-1], device="cuda")
         costs = t.empty(K_off[-1], device="cuda")
         B.gpmppi_batch_step(b, dev(x0), dev(U), seed, Uo, costs)
@@ -126,7 +126,7 @@ def test_batch_autotuner_choice_keeps_results_of_the_matching_single_shape():
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     for i, p in enumerate(ps):
         ctx = B.gpmppi_init(p, B.FP32)
-        B.gpmppi_set_tuning(ctx, chosen["groups"], chosen["rotate"])
+        B.gpmppi_set_tuning(ctx, chosen["groups"], chosen["rotate"], chosen["waves"])
         U1, S1, _ = gpu_step(p, B.FP32, seed=seed, ctx=ctx)
         np.testing.assert_array_equal(outs[0][1][K_off[i]:K_off[i + 1]].astype(np.float64), S1)
         np.testing.assert_array_equal(outs[0][0][U_off[i]:U_off[i + 1]].reshape(-1, 2).astype(np.float64), U1)
@@ -134,6 +134,7 @@ def test_batch_autotuner_choice_keeps_results_of_the_matching_single_shape():
 
 def test_batch_tuning_rejects_inadmissible_shapes():
     b = B.gpmppi_batch_init(_problems(), B.FP32)
-    for bad in ((0, 1, 1, 0), (3, 1, 1, 0), (1, 2, 1, 0), (1, 1, 0, 0), (1, 1, 3, 0), (1, 1, 1, 2)):
+    for bad in ((0, 1, 1, 0, 4), (3, 1, 1, 0, 4), (1, 2, 1, 0, 4), (1, 1, 0, 0, 4), (1, 1, 3, 0, 4), (1, 1, 1, 2, 4),
+                (1, 1, 1, 0, 6)):
         with pytest.raises(B.GpmppiError):
             B.gpmppi_batch_set_tuning(b, *bad)
