@@ -9,6 +9,9 @@ namespace gpmppi {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+// read-only kernel data at wave-uniform addresses: loads through the scalar cache
+typedef const __attribute__((address_space(4))) v4f *const_v4p;
+typedef const __attribute__((address_space(4))) float *const_fp;
 
 constexpr int kSamplesPerBlock = 32;   // samples per workgroup (one MFMA column block)
 constexpr int kThreads = 256;          // 4 wave64s

@@ -358,13 +358,84 @@ __global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int
     cza[2 * j + 1] = (float)a;
 }
 
-hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
-                          float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
+// Three BF16 terms whose sum is the FP32 value x (round to nearest even at
+// each stage; each remainder is exact in FP32).
+__device__ __forceinline__ void split3_bf16(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
+    const __bf16 bh = (__bf16)x;
+    const float r1 = x - (float)bh;
+    const __bf16 bm = (__bf16)r1;
+    const float r2 = r1 - (float)bm;
+    const __bf16 bl = (__bf16)r2;
+    __builtin_memcpy(&h, &bh, 2);
+    __builtin_memcpy(&m, &bm, 2);
+    __builtin_memcpy(&l, &bl, 2);
+}
+
+// A operands of the exponent products of the BF16 form.  For column tile jt
+// the kernel-vector exponent of point j and sample s,
+//   e_js = (c2 - |zs_j|^2) - |qs_s|^2 + sum_d (2 zs_jd) qs_sd,
+// is the 32 x 32 product of two 32 x 32 x 16 matrix-core steps with the FP32
+// factors split into three BF16 terms (h + m + l); the kept partial products
+// hh, hm, mh, hl, mm, lh carry every bit down to 2^-24 of each factor:
+//   step 0 slots:  0-3 zh   4-7 zh   8-11 zm   12-15 zh        (B: qh qm qh ql)
+//   step 1 slots:  0-3 zm   4-7 zl   8-10 (c2 - |zs|^2) h m l, 11-13 one, 14-15 zero
+//                                                              (B: qm qh 1 1 1 -qq h m l 0 0)
+// Row rho of a tile holds point 32 jt + P(rho), P(8a + 4b + c) = 16 (a / 2) + 8 b + 4 (a % 2) + c,
+// so that lane l of the product's accumulator (rows 8(r/4) + 4(l/32) + r%4) ends
+// up with points 8 (l / 32) + r (r < 8) and 16 + 8 (l / 32) + r - 8: the k operand
+// of the variance products in its lane order without any exchange.
+// zop[(jt * 2 + step) * 64 + lane] = 8 BF16 slots 8 (lane / 32) .. + 7 of row lane % 32.
+__global__ void pack_zop_kernel(const float *zs2, const float *cza, int Mpad, uint4 *zop) {
+    const int NT = Mpad / 32;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NT * 128) return;
+    const int lane = i & 63, step = (i >> 6) & 1, jt = i >> 7;
+    const int rho = lane & 31, half = lane >> 5;
+    const int a = rho >> 3, bb = (rho >> 2) & 1, c = rho & 3;
+    const int j = 32 * jt + 16 * (a >> 1) + 8 * bb + 4 * (a & 1) + c;
+    uint16_t zh[4], zm[4], zl[4], ch, cm, cl;
+    for (int d = 0; d < 4; ++d) split3_bf16(zs2[4 * j + d], zh[d], zm[d], zl[d]);
+    split3_bf16(cza[2 * j], ch, cm, cl);
+    const uint16_t one = 0x3f80;
+    uint16_t slot[16];
+    if (step == 0) {
+        for (int d = 0; d < 4; ++d) {
+            slot[d] = zh[d];
+            slot[4 + d] = zh[d];
+            slot[8 + d] = zm[d];
+            slot[12 + d] = zh[d];
+        }
+    } else {
+        for (int d = 0; d < 4; ++d) {
+            slot[d] = zm[d];
+            slot[4 + d] = zl[d];
+        }
+        slot[8] = ch;
+        slot[9] = cm;
+        slot[10] = cl;
+        slot[11] = one;
+        slot[12] = one;
+        slot[13] = one;
+        slot[14] = 0;
+        slot[15] = 0;
+    }
+    const uint16_t *sv = slot + 8 * half;
+    uint4 v;
+    v.x = sv[0] | ((uint32_t)sv[1] << 16);
+    v.y = sv[2] | ((uint32_t)sv[3] << 16);
+    v.z = sv[4] | ((uint32_t)sv[5] << 16);
+    v.w = sv[6] | ((uint32_t)sv[7] << 16);
+    zop[i] = v;
+}
+
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, uint4 *zop,
+                          float *zs, float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
                           hipStream_t st) {
     const int NP = (Mpad / 32 + 1) / 2;
     hipLaunchKernelGGL(pack_w_kernel, dim3(2 * NP * (NP + 1)), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
     hipLaunchKernelGGL(pack_vec_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.Z, b.alpha, M, Mpad,
                        scale[0], scale[1], scale[2], scale[3], c2, zs, alpha, zs2, cza);
+    hipLaunchKernelGGL(pack_zop_kernel, dim3((Mpad / 32 * 128 + 255) / 256), dim3(256), 0, st, zs2, cza, Mpad, zop);
     return hipGetLastError();
 }
 

@@ -203,6 +203,8 @@ __device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0
 }
 
 __device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (c.u + 1) + c.it); }
+// The pair's last column tile: its block (2u, 2u + 1) lies above the diagonal.
+__device__ __forceinline__ bool pair_zero(const Cursor &c) { return c.it == 2 * c.u + 1; }
 
 
 template <int PREC>
@@ -214,13 +216,38 @@ struct Shapes {
     static constexpr int waves = NW;              // wave64s per workgroup
     static constexpr int threads = 64 * NW;
     static constexpr int parts = NW * (2 / G);    // loop splitters: waves (x half-waves for G = 1)
+    static constexpr int rparts = 2 * NW;         // partial sums per sample in the reduction arrays
     static constexpr int stage_iters = (1536 + threads - 1) / threads;   // staged-input slots per thread
 };
 
-// Dynamic LDS layout: [G k-operand groups][zs: Mpad float4][alpha: Mpad float]
+// Per-point GP inputs: with two sample groups a wave's chunks of training
+// points are wave-uniform, so the inputs are read through the scalar cache
+// straight from global memory; with one group the two half-waves take
+// different chunks and the inputs are staged in LDS.
+template <int G>
+__host__ __device__ constexpr bool scalar_inputs() { return G == 2; }
+
+// The BF16 form computes the kernel-vector exponents on the matrix cores from
+// prepacked point operands (GpDev::zop) and needs only alpha of both outputs
+// in LDS, staged once per launch.
+template <int PREC>
+__host__ __device__ constexpr bool mfma_gen() { return PREC == GPMPPI_BF16; }
+
+// Dynamic LDS layout: [G k-operand groups] then alpha [2][Mpad] (BF16 form),
+// nothing (scalar-cache inputs) or the per-point inputs of one output.
 template <int PREC, int G>
 __host__ __device__ constexpr size_t dyn_lds_bytes(int Mpad) {
-    return G * kgroup_bytes<PREC>(Mpad) + (size_t)staged_slots<PREC>(Mpad) * 16;
+    return G * kgroup_bytes<PREC>(Mpad) +
+           (mfma_gen<PREC>() ? (size_t)2 * Mpad * 4
+                             : (scalar_inputs<G>() ? 0 : (size_t)staged_slots<PREC>(Mpad) * 16));
+}
+
+// Copies alpha of both outputs to LDS (all threads; the caller synchronises).
+template <int NW>
+__device__ __forceinline__ void stage_alpha(const GpDev &g, unsigned char *lds, size_t off) {
+    const v4f *src = reinterpret_cast<const v4f *>(g.alpha);
+    v4f *dst = reinterpret_cast<v4f *>(lds + off);
+    for (int i = threadIdx.x; i < g.Mpad / 2; i += 64 * NW) dst[i] = src[i];
 }
 
 // One GP output for the B samples of the block; called by all threads.
@@ -274,6 +301,22 @@ __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev 
     }
 }
 
+// BF16 bit patterns of three terms summing to the FP32 value x (round to
+// nearest even at each stage; the remainders are exact in FP32).
+__device__ __forceinline__ void split3_bits(float x, uint32_t &h, uint32_t &m, uint32_t &l) {
+    const __bf16 bh = (__bf16)x;
+    const float r1 = x - (float)bh;
+    const __bf16 bm = (__bf16)r1;
+    const __bf16 bl = (__bf16)(r1 - (float)bm);
+    uint16_t u;
+    __builtin_memcpy(&u, &bh, 2);
+    h = u;
+    __builtin_memcpy(&u, &bm, 2);
+    m = u;
+    __builtin_memcpy(&u, &bl, 2);
+    l = u;
+}
+
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
     typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
     typedef float v2f __attribute__((ext_vector_type(2)));
@@ -293,21 +336,24 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                                           bool rev, int rotate, int blk, unsigned char *lds, float *pred,
                                           float *vred, float &mean_out, float &var_out) {
     using S = Shapes<PREC, G, NW>;
+    constexpr bool kScalar = scalar_inputs<G>();
     const int Mpad = g.Mpad;
     const int nchunk = Mpad >> 3;
-    const float4 *zs = reinterpret_cast<const float4 *>(lds + G * kgroup_bytes<PREC>(Mpad));
+    const v4f *zs = reinterpret_cast<const v4f *>(lds + G * kgroup_bytes<PREC>(Mpad));   // staged inputs
     const int grp = sl >> 5, s32 = sl & 31;
     unsigned char *kg = lds + grp * kgroup_bytes<PREC>(Mpad);
+    const int c0 = kScalar ? __builtin_amdgcn_readfirstlane(part) : part;
     float msum = 0.0f;
     if constexpr (PREC == GPMPPI_FP32) {
         // exact differences: k = exp2(c2 - sum_d (q_d - zs_d)^2)
-        const float *al = reinterpret_cast<const float *>(zs + Mpad);
+        const const_v4p zsg = (const_v4p)g.zs + (size_t)o * Mpad;
+        const const_v4p alg = (const_v4p)(g.alpha + (size_t)o * Mpad);
         const float c2 = g.c2[o];
-        for (int c = part; c < nchunk; c += S::parts) {
+        for (int c = c0; c < nchunk; c += S::parts) {
             float kv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float4 z = zs[8 * c + e];
+                const v4f z = kScalar ? zsg[8 * c + e] : zs[8 * c + e];
                 const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
                 float acc = c2;
                 acc = fmaf(-d0, d0, acc);
@@ -316,8 +362,8 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                 acc = fmaf(-d3, d3, acc);
                 kv[e] = __builtin_amdgcn_exp2f(acc);
             }
-            const float4 a0 = *reinterpret_cast<const float4 *>(al + 8 * c);
-            const float4 a1 = *reinterpret_cast<const float4 *>(al + 8 * c + 4);
+            const v4f a0 = kScalar ? alg[2 * c] : zs[Mpad + 2 * c];
+            const v4f a1 = kScalar ? alg[2 * c + 1] : zs[Mpad + 2 * c + 1];
             msum = fmaf(kv[0], a0.x, msum);
             msum = fmaf(kv[1], a0.y, msum);
             msum = fmaf(kv[2], a0.z, msum);
@@ -330,25 +376,87 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
             K[s32] = make_float4(kv[0], kv[2], kv[4], kv[6]);
             K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
         }
+    } else if constexpr (mfma_gen<PREC>()) {
+        // exponents on the matrix cores: two 32x32x16 BF16 products per 32-point column
+        // tile and sample group with the FP32 factors split into three BF16 terms (the
+        // operand layout is described at pack_zop_kernel); exp2, the mean and the BF16
+        // k operand on the VALU.  Lane l: sample 32 g + l % 32, points 8 (l / 32) + r
+        // (r < 8) and 16 + 8 (l / 32) + r - 8 of the tile.
+        const int lane = threadIdx.x & 63, hl = lane >> 5;
+        const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const float *al = reinterpret_cast<const float *>(lds + G * kgroup_bytes<PREC>(Mpad)) + (size_t)o * Mpad;
+        const uint4 *zop = g.zop + o * g.zop_stride;
+        uint4 bop[G][2];
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            float qv[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const float other = (G == 2) ? shfl_xor(qs[d], 32) : qs[d];
+                qv[d] = (G == 1 || hl == gg) ? qs[d] : other;
+            }
+            const float qq = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
+            uint32_t qh[4], qm[4], ql[4], nqq[3];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) split3_bits(qv[d], qh[d], qm[d], ql[d]);
+            split3_bits(-qq, nqq[0], nqq[1], nqq[2]);
+            const uint32_t one = 0x3f80u;
+            if (hl == 0) {   // slots 0-7 of both products: (qh, qm) and (qm, qh)
+                bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, qm[0] | qm[1] << 16, qm[2] | qm[3] << 16);
+                bop[gg][1] = make_uint4(qm[0] | qm[1] << 16, qm[2] | qm[3] << 16, qh[0] | qh[1] << 16, qh[2] | qh[3] << 16);
+            } else {         // slots 8-15: (qh, ql) and (1, 1, 1, -qq h, -qq m, -qq l, 0, 0)
+                bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, ql[0] | ql[1] << 16, ql[2] | ql[3] << 16);
+                bop[gg][1] = make_uint4(one | one << 16, one | nqq[0] << 16, nqq[1] | nqq[2] << 16, 0u);
+            }
+        }
+        float ms[G];
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) ms[gg] = 0.0f;
+        for (int jt = wv; jt < g.NT; jt += NW) {
+            const uint4 a0 = zop[(jt * 2) * 64 + lane];
+            const uint4 a1 = zop[(jt * 2 + 1) * 64 + lane];
+            const v4f *ap = reinterpret_cast<const v4f *>(al + 32 * jt + 8 * hl);
+            const v4f alv[4] = {ap[0], ap[1], ap[4], ap[5]};
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                v16f e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a0), as_bf(bop[gg][0]), v16f{}, 0, 0, 0);
+                e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a1), as_bf(bop[gg][1]), e, 0, 0, 0);
+                float kv[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) kv[r] = __builtin_amdgcn_exp2f(e[r]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) ms[gg] = fmaf(kv[r], alv[r >> 2][r & 3], ms[gg]);
+                uint4 *K = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad)) + (size_t)jt * 128;
+                K[lane] = make_uint4(pack_bf16x2(kv[0], kv[1]), pack_bf16x2(kv[2], kv[3]), pack_bf16x2(kv[4], kv[5]),
+                                     pack_bf16x2(kv[6], kv[7]));
+                K[64 + lane] = make_uint4(pack_bf16x2(kv[8], kv[9]), pack_bf16x2(kv[10], kv[11]),
+                                          pack_bf16x2(kv[12], kv[13]), pack_bf16x2(kv[14], kv[15]));
+            }
+        }
+        // partial means per (wave, half-wave) for each group's sample
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) pred[(wv * 2 + hl) * S::B + 32 * gg + (lane & 31)] = ms[gg];
     } else {
         // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs) = c2 - |q - zs|^2 <= c2 up to
         // rounding, so exp2 needs no clamp; its FP32 rounding (~1e-6 relative in k)
         // is far below the BF16 operand rounding (2^-9)
-        const float4 *cza = zs + Mpad;   // (c2 - |zs|^2, alpha) pairs
+        const v4f *cza = zs + Mpad;   // staged (c2 - |zs|^2, alpha) pairs
+        const const_v4p zsg = (const_v4p)g.zs2 + (size_t)o * Mpad;
+        const const_v4p czg = (const_v4p)(g.cza + (size_t)o * Mpad * 2);
         const float qq = qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3];
-        for (int c = part; c < nchunk; c += S::parts) {
+        for (int c = c0; c < nchunk; c += S::parts) {
             float kv[8];
             float al8[8];
 #pragma unroll
             for (int e2 = 0; e2 < 4; ++e2) {
-                const float4 ca = cza[4 * c + e2];
+                const v4f ca = kScalar ? czg[4 * c + e2] : cza[4 * c + e2];
                 al8[2 * e2] = ca.y;
                 al8[2 * e2 + 1] = ca.w;
                 const float cz[2] = {ca.x, ca.z};
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int e = 2 * e2 + h;
-                    const float4 z2 = zs[8 * c + e];
+                    const v4f z2 = kScalar ? zsg[8 * c + e] : zs[8 * c + e];
                     float acc = cz[h] - qq;
                     acc = fmaf(qs[0], z2.x, acc);
                     acc = fmaf(qs[1], z2.y, acc);
@@ -377,10 +485,12 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         }
     }
     // per-part partial means: the lanes of a part hold distinct samples
-    pred[part * S::B + sl] = msum;
+    if constexpr (!mfma_gen<PREC>()) pred[part * S::B + sl] = msum;
     __syncthreads();
     StagedInputs st;
-    if (next_o >= 0) stage_load<PREC, NW>(st, g, next_o);
+    if constexpr (!kScalar && !mfma_gen<PREC>()) {
+        if (next_o >= 0) stage_load<PREC, NW>(st, g, next_o);
+    }
 
     // ---- variance contraction on the matrix cores
     const int lane = threadIdx.x & 63;
@@ -410,13 +520,15 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     }
     bool pair_start = true;
     Cursor pc, mc;   // prefetch and compute cursors
+    int last_b0 = 0;
     if (nit > 0) {
         cursor_start<NW>(pc, w, npairs, r0, rev);
         cursor_start<NW>(mc, w, npairs, r0, rev);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int b0 = pair_block(pc);
-            load_wblock<PREC>(ring[r][0], g, o, b0, lane);
+            last_b0 = b0;
+            load_wblock<PREC>(ring[r][0], g, o, pair_zero(pc) ? b0 + 1 : b0, lane);
             load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
             cursor_next<NW>(pc, w, npairs, r0, rev);
         }
@@ -426,31 +538,44 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     for (int base = 0; base < nit; base += 2) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            // this iteration's products; a pair's first iteration starts from zero
+            // this iteration's products; a pair's first iteration starts from zero, and
+            // the block above the diagonal (zero) is neither loaded nor multiplied
+            const bool zt = pair_zero(mc);
             if (pair_start) {
+                if (zt) {
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) {
-                    acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
-                    acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
+                    for (int gg = 0; gg < G; ++gg) acc[0][gg] = v16f{};
+                } else {
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
                 }
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
             } else {
+                if (!zt) {
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) {
-                    mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
-                    mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
+                    for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
                 }
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
             }
-            // refill this ring slot two iterations ahead, the other k slot one ahead
-            if (base + r + 2 < nit) {
-                const int b0 = pair_block(pc);
-                load_wblock<PREC>(ring[r][0], g, o, b0, lane);
+            // refill this ring slot two iterations ahead, the other k slot one ahead.
+            // Every iteration issues the same loads (past the end and in place of the
+            // zero block they repeat a block already fetched), so the memory counters
+            // stay exact and the wait before each product is for its own operands only.
+            {
+                const bool live = base + r + 2 < nit;
+                const int b0 = live ? pair_block(pc) : last_b0;
+                const bool z = live && pair_zero(pc);
+                load_wblock<PREC>(ring[r][0], g, o, z ? b0 + 1 : b0, lane);
                 load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-                cursor_next<NW>(pc, w, npairs, r0, rev);
+                if (live) cursor_next<NW>(pc, w, npairs, r0, rev);
             }
             const bool pair_end = cursor_next<NW>(mc, w, npairs, r0, rev);
-            if (base + r + 1 < nit) {
+            {
+                const int kit = base + r + 1 < nit ? mc.it : 0;
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], mc.it, lane, Mpad);
+                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], kit, lane, Mpad);
             }
             pair_start = pair_end;
             if (pair_end) {
@@ -471,12 +596,15 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
     }
     __syncthreads();
-    if (next_o >= 0) stage_store<PREC, NW>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
+    if constexpr (!kScalar && !mfma_gen<PREC>()) {
+        if (next_o >= 0) stage_store<PREC, NW>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
+    }
     float v2 = 0.0f, m = 0.0f;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) v2 += vred[ww * S::B + sl];
+    constexpr int mparts = mfma_gen<PREC>() ? S::rparts : S::parts;
 #pragma unroll
-    for (int p = 0; p < S::parts; ++p) m += pred[p * S::B + sl];
+    for (int p = 0; p < mparts; ++p) m += pred[p * S::B + sl];
     var_out = g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));
     mean_out = m;
 }

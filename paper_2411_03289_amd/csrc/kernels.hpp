@@ -26,8 +26,10 @@ struct GpDev {
     const float4 *w32;
     const uint4 *wbh;
     const uint4 *wbl;
+    const uint4 *zop;       // BF16 A operands of the exponent products [2][NT][2][64] (see pack_zop_kernel)
     long long w32_stride;   // float4 per output
     long long wb_stride;    // uint4 per output
+    long long zop_stride;   // uint4 per output (NT * 128)
     float scale[2][4];
     float c2[2];
     float sf2[2];
@@ -182,7 +184,7 @@ hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st);
 // Q = A^-1 = W^T W packed dense (FP32 operand order); overwrites b.A.
 hipError_t pack_q(const GpBuildBuffers &b, int M, int Mpad, float4 *q32, hipStream_t st);
 hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st);
-hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, float *zs,
+hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, uint4 *zop, float *zs,
                           float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
                           hipStream_t st);
 

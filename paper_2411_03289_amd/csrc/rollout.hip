@@ -26,6 +26,22 @@
 
 namespace gpmppi {
 
+// Tightened distance to one obstacle (Eqs. 14, 16): the centre distance rho
+// less the radius, less z_p times the position deviation along the centre
+// direction n = (dx, dy) / rho, n^T Sigma n = (sa dx^2 + 2 sb dx dy + sc dy^2) / rho^2;
+// at rho = 0 the direction is undefined and the largest eigenvalue stands in.
+// One reciprocal square root gives both rho and 1 / rho^2.
+__device__ __forceinline__ float obstacle_margin(float dx, float dy, float radius, float sa, float sb, float sc,
+                                                 float lmax, float z_p) {
+    const float rho2 = dx * dx + dy * dy;
+    const bool pos = rho2 > 0.0f;
+    const float rs = __builtin_amdgcn_rsqf(rho2);
+    const float rho = pos ? rho2 * rs : 0.0f;
+    const float quad = sa * dx * dx + 2.0f * sb * dx * dy + sc * dy * dy;
+    const float vn = pos ? quad * (rs * rs) : lmax;
+    return (rho - radius) - z_p * __builtin_amdgcn_sqrtf(fmaxf(vn, 0.0f));
+}
+
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
 // problem; called by all threads of a workgroup.
 template <int PREC, int G, int NW = kWaves>
@@ -74,7 +90,9 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         a.trace.sxy_d[2 * K + sg] = 0.0f;
     }
 
-    {   // inputs of output 0 (the first output of step 0)
+    if constexpr (mfma_gen<PREC>()) {   // alpha of both outputs, for the whole horizon
+        stage_alpha<NW>(a.gp, lds, zs_off);
+    } else if constexpr (!scalar_inputs<G>()) {   // inputs of output 0 (the first output of step 0)
         StagedInputs st;
         stage_load<PREC, NW>(st, a.gp, 0);
         stage_store<PREC, NW>(st, a.gp, lds, zs_off);
@@ -145,24 +163,43 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
         float best = INFINITY;   // squared distance to the polyline (this part's segments)
-        if (geo.path_kind != 0) {
-            for (int i = (G == 2 ? wu : part); i < geo.P; i += S::parts) {
-                const float4 sgm = geo.seg[i];
-                const float rx = X - sgm.x, ry = Y - sgm.y;
-                float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
-                t = fminf(fmaxf(t, 0.0f), 1.0f);
-                const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
-                best = fminf(best, ex * ex + ey * ey);
+        float om = INFINITY;     // least tightened obstacle distance (this part's obstacles)
+        if constexpr (G == 2) {
+            // wave-uniform indices: segments and obstacles come through the scalar cache
+            if (geo.path_kind != 0) {
+                const const_v4p segs = (const_v4p)geo.seg;
+                const const_fp sinv = (const_fp)geo.seg_inv;
+#pragma unroll 4
+                for (int i = wu; i < geo.P; i += S::parts) {
+                    const v4f sgm = segs[i];
+                    const float rx = X - sgm.x, ry = Y - sgm.y;
+                    float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
+                    t = fminf(fmaxf(t, 0.0f), 1.0f);
+                    const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
+                    best = fminf(best, ex * ex + ey * ey);
+                }
             }
-        }
-        float om = INFINITY;
-        for (int j = (G == 2 ? wu : part); j < geo.n_obs; j += S::parts) {
-            const float4 ob = geo.obs[j];
-            const float dx = X - ob.x, dyy = Y - ob.y;
-            const float rho2 = dx * dx + dyy * dyy;
-            const float rho = sqrtf(rho2);
-            const float vn_dir = rho > 0.0f ? (sa * dx * dx + 2.0f * sb * dx * dyy + sc * dyy * dyy) / rho2 : lmax;
-            om = fminf(om, (rho - ob.z) - geo.z_p * sqrtf(fmaxf(vn_dir, 0.0f)));
+            const const_v4p obs = (const_v4p)geo.obs;
+#pragma unroll 2
+            for (int j = wu; j < geo.n_obs; j += S::parts) {
+                const v4f ob = obs[j];
+                om = fminf(om, obstacle_margin(X - ob.x, Y - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
+            }
+        } else {
+            if (geo.path_kind != 0) {
+                for (int i = part; i < geo.P; i += S::parts) {
+                    const float4 sgm = geo.seg[i];
+                    const float rx = X - sgm.x, ry = Y - sgm.y;
+                    float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
+                    t = fminf(fmaxf(t, 0.0f), 1.0f);
+                    const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
+                    best = fminf(best, ex * ex + ey * ey);
+                }
+            }
+            for (int j = part; j < geo.n_obs; j += S::parts) {
+                const float4 ob = geo.obs[j];
+                om = fminf(om, obstacle_margin(X - ob.x, Y - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
+            }
         }
         __syncthreads();   // readers of the last output's partial sums are done
         pred[part * S::B + sl] = best;
@@ -248,7 +285,7 @@ template <int PREC, int G, int NW>
 __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float pred[S::parts * S::B];
+    __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[S::parts * S::B];
     __shared__ float vred[NW * S::B];
     rollout_block<PREC, G, NW>(a, blockIdx.x, lds, pred, ored, vred);
@@ -263,7 +300,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(const RolloutArg
                                                                  int n_items, uint32_t *counter) {
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float pred[S::parts * S::B];
+    __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[S::parts * S::B];
     __shared__ float vred[NW * S::B];
     __shared__ int next_item;
@@ -285,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const flo
                                                               float *var) {
     using S = Shapes<PREC, G>;
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ float pred[S::parts * S::B];
+    __shared__ float pred[S::rparts * S::B];
     __shared__ float vred[kWaves * S::B];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -296,7 +333,9 @@ __global__ __launch_bounds__(kThreads) void gp_predict_kernel(GpDev g, const flo
     const float4 qq = reinterpret_cast<const float4 *>(q)[sc];
     const float qv[4] = {qq.x, qq.y, qq.z, qq.w};
     const size_t zs_off = G * kgroup_bytes<PREC>(g.Mpad);
-    {
+    if constexpr (mfma_gen<PREC>()) {
+        stage_alpha<kWaves>(g, lds, zs_off);
+    } else if constexpr (!scalar_inputs<G>()) {
         StagedInputs st;
         stage_load<PREC>(st, g, 0);
         stage_store<PREC>(st, g, lds, zs_off);

@@ -88,7 +88,8 @@ struct gpmppi_ctx {
     int rotate = 1;                  // block-dependent start of the walk over W (tuned)
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
-    long long w32_stride = 0, wb_stride = 0;
+    uint4 *zop = nullptr;            // BF16 exponent-product operands per output
+    long long w32_stride = 0, wb_stride = 0, zop_stride = 0;
     float4 *q32 = nullptr;           // dense packed Q = A^-1 per output (differentiation form, Mpad <= 512)
     long long q_stride = 0;          // float4 per output
     void *grad_ws = nullptr;         // differentiation-form workspace (grown on demand)
@@ -229,7 +230,8 @@ gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
         HIP_TRY(hipMemcpy(&notpd, c->flags + 1, sizeof notpd, hipMemcpyDeviceToHost));
         if (notpd) return fail(GPMPPI_E_NOT_PD, "GP %d: K(Z,Z) + sn^2 I is not positive definite", o);
         const double c2 = 2.0 * gp[o].log_sf / std::log(2.0);
-        HIP_TRY(pack_gp_output(b, M, Mpad, scale, c2, c->zs + (size_t)o * Mpad * 4, c->alpha + (size_t)o * Mpad,
+        HIP_TRY(pack_gp_output(b, M, Mpad, scale, c2, c->zop + o * c->zop_stride, c->zs + (size_t)o * Mpad * 4,
+                               c->alpha + (size_t)o * Mpad,
                                c->zs2 + (size_t)o * Mpad * 4, c->cza + (size_t)o * Mpad * 2,
                                c->w32 + o * c->w32_stride, c->wbh + o * c->wb_stride, c->wbl + o * c->wb_stride,
                                nullptr));
@@ -352,6 +354,8 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->w32 = track(dev_alloc<float4>((size_t)2 * c->w32_stride, st));
     c->wbh = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
     c->wbl = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
+    c->zop_stride = (long long)(Mpad / 32) * 128;
+    c->zop = track(dev_alloc<uint4>((size_t)2 * c->zop_stride, st));
     if (Mpad <= kGradMaxMpad) {
         c->q_stride = (long long)(Mpad / 32) * (Mpad / 32) * 256;
         c->q32 = track(dev_alloc<float4>((size_t)2 * c->q_stride, st));
@@ -410,6 +414,8 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->gp.wbl = c->wbl;
     c->gp.w32_stride = c->w32_stride;
     c->gp.wb_stride = c->wb_stride;
+    c->gp.zop = c->zop;
+    c->gp.zop_stride = c->zop_stride;
     c->gp.Mpad = Mpad;
     c->groups = rollout_groups(params->precision, Mpad);
     c->gp.NT = NT;
