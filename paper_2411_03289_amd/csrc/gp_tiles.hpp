@@ -127,6 +127,11 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
     }
 }
 
+// Depth of the walk's W register ring (iterations in flight).  Two keep the
+// matrix cores fed on gfx950; three measured no faster for the BF16 form.
+template <int PREC, int G>
+__host__ __device__ constexpr int walk_depth() { return 2; }
+
 // The products of a pair's first iteration, accumulated onto zero.
 template <int PREC>
 __device__ __forceinline__ v16f mma_first(const WBlock<PREC> &b, const KOp<PREC> &k) {
@@ -164,48 +169,105 @@ __device__ __forceinline__ v16f mma_first(const WBlock<PREC> &b, const KOp<PREC>
 template <int NW>
 __device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? NW * i + NW - 1 - w : NW * i + w; }
 
-// Position in a wave's iteration sequence: n pairs visited so far, list
-// index i = (r0 + n) mod npairs (forward) or (r0 - 1 - n) mod npairs
-// (reverse), pair u and iteration it.  Forward: pairs in list order from r0,
-// it ascending; reverse: the exact reverse of that sequence.  Every pair has
-// an even length.
+// Position in a wave's iteration sequence.  The wave's pairs, in visiting
+// order, are packed 8 bits each into plist (at most 8 pairs: Mpad <= 1024);
+// forward: pairs in order, it ascending; reverse: the exact reverse of that
+// sequence.  Every pair has an even length.  The list is built once per output
+// so that an iteration costs a few scalar additions and compares; past the
+// end the cursor sits on pair 0 (a valid block).
 struct Cursor {
-    int n, i, u, it;
+    int n;      // pairs completed
+    int it;     // current column tile
+    int last;   // 2u + 1 for the current pair u
+    int base;   // packed index of block (2u, 0): 2 u (u + 1)
 };
 
-template <int NW>
-__device__ __forceinline__ void cursor_set(Cursor &c, int w, int npairs, int r0, bool rev) {
-    int i = rev ? r0 - 1 - c.n : r0 + c.n;
-    i %= npairs;
-    if (i < 0) i += npairs;
-    c.i = i;
-    c.u = wave_pair<NW>(w, i);
-    c.it = rev ? 2 * c.u + 1 : 0;
+__device__ __forceinline__ void cursor_pair(Cursor &c, uint64_t plist, bool rev) {
+    const int u = (int)((plist >> (8 * (c.n & 7))) & 0xFFu);
+    c.last = 2 * u + 1;
+    c.base = 2 * u * (u + 1);
+    c.it = rev ? c.last : 0;
 }
 
-template <int NW>
-__device__ __forceinline__ void cursor_start(Cursor &c, int w, int npairs, int r0, bool rev) {
+__device__ __forceinline__ void cursor_start(Cursor &c, uint64_t plist, bool rev) {
     c.n = 0;
-    cursor_set<NW>(c, w, npairs, r0, rev);
+    cursor_pair(c, plist, rev);
 }
 
 // Advances; returns true when the iteration just left closed its pair.
-template <int NW>
-__device__ __forceinline__ bool cursor_next(Cursor &c, int w, int npairs, int r0, bool rev) {
+__device__ __forceinline__ bool cursor_next(Cursor &c, uint64_t plist, bool rev) {
     if (!rev) {
-        if (++c.it <= 2 * c.u + 1) return false;
+        if (++c.it <= c.last) return false;
     } else {
         if (--c.it >= 0) return false;
     }
     ++c.n;
-    cursor_set<NW>(c, w, npairs, r0, rev);
+    cursor_pair(c, plist, rev);
     return true;
 }
 
-__device__ __forceinline__ int pair_block(const Cursor &c) { return 2 * (c.u * (c.u + 1) + c.it); }
+__device__ __forceinline__ int pair_block(const Cursor &c) { return c.base + 2 * c.it; }
 // The pair's last column tile: its block (2u, 2u + 1) lies above the diagonal.
-__device__ __forceinline__ bool pair_zero(const Cursor &c) { return c.it == 2 * c.u + 1; }
+__device__ __forceinline__ bool pair_zero(const Cursor &c) { return c.it == c.last; }
 
+// Buffer resources over one output's packed W: the block offset goes in the
+// scalar offset, the lane offset stays in one VGPR, out-of-range reads return 0.
+template <int PREC>
+struct WRsrc {
+    __amdgpu_buffer_rsrc_t h, l;
+};
+
+// Descriptor from wave-uniform base and size (the persistent batch kernel reads
+// its GpDev from memory, where the compiler cannot prove uniformity and would
+// otherwise wrap every load in a readfirstlane loop).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *base, long long bytes) {
+    constexpr int kFlags = 0x00020000;   // raw (untyped) buffer, dword 3 of the descriptor
+    const uint64_t a = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const int n = __builtin_amdgcn_readfirstlane((int)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)(((uint64_t)hi << 32) | lo), (short)0, n, kFlags);
+}
+
+template <int PREC>
+__device__ __forceinline__ WRsrc<PREC> w_rsrc(const GpDev &g, int o) {
+    WRsrc<PREC> r;
+    if constexpr (PREC == GPMPPI_FP32) {
+        r.h = uniform_rsrc(g.w32 + o * g.w32_stride, g.w32_stride * 16);
+        r.l = r.h;
+    } else {
+        r.h = uniform_rsrc(g.wbh + o * g.wb_stride, g.wb_stride * 16);
+        r.l = PREC == GPMPPI_BF16X3 ? uniform_rsrc(g.wbl + o * g.wb_stride, g.wb_stride * 16) : r.h;
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint4 buf_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const v4u t = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    uint4 u;
+    __builtin_memcpy(&u, &t, 16);
+    return u;
+}
+
+// W block blk of the packed layout for lane offset voff = 16 * lane.
+template <int PREC>
+__device__ __forceinline__ void load_wblock_rs(WBlock<PREC> &b, const WRsrc<PREC> &rs, int blk, int voff) {
+    if constexpr (PREC == GPMPPI_FP32) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 t = buf_load16(rs.h, voff + 1024 * q, blk * 4096);
+            __builtin_memcpy(&b.v[q], &t, 16);
+        }
+    } else {
+        b.h[0] = buf_load16(rs.h, voff, blk * 2048);
+        b.h[1] = buf_load16(rs.h, voff + 1024, blk * 2048);
+        if constexpr (PREC == GPMPPI_BF16X3) {
+            b.l[0] = buf_load16(rs.l, voff, blk * 2048);
+            b.l[1] = buf_load16(rs.l, voff + 1024, blk * 2048);
+        }
+    }
+}
 
 template <int PREC>
 __host__ __device__ constexpr int staged_slots(int Mpad);
@@ -412,11 +474,20 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         float ms[G];
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) ms[gg] = 0.0f;
+        // operands of this wave's tiles jt = wv, wv + NW, ..., each fetched one tile ahead
+        // (the fetch after the last tile repeats it, keeping the counters exact)
+        int jc = wv < g.NT ? wv : g.NT - 1;
+        uint4 a0 = zop[(jc * 2) * 64 + lane], a1 = zop[(jc * 2 + 1) * 64 + lane];
+        v4f alv[4];
+        {
+            const v4f *ap = reinterpret_cast<const v4f *>(al + 32 * jc + 8 * hl);
+            alv[0] = ap[0]; alv[1] = ap[1]; alv[2] = ap[4]; alv[3] = ap[5];
+        }
         for (int jt = wv; jt < g.NT; jt += NW) {
-            const uint4 a0 = zop[(jt * 2) * 64 + lane];
-            const uint4 a1 = zop[(jt * 2 + 1) * 64 + lane];
-            const v4f *ap = reinterpret_cast<const v4f *>(al + 32 * jt + 8 * hl);
-            const v4f alv[4] = {ap[0], ap[1], ap[4], ap[5]};
+            const int jn = jt + NW < g.NT ? jt + NW : jt;
+            const uint4 n0 = zop[(jn * 2) * 64 + lane], n1 = zop[(jn * 2 + 1) * 64 + lane];
+            const v4f *apn = reinterpret_cast<const v4f *>(al + 32 * jn + 8 * hl);
+            const v4f aln[4] = {apn[0], apn[1], apn[4], apn[5]};
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) {
                 v16f e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a0), as_bf(bop[gg][0]), v16f{}, 0, 0, 0);
@@ -432,6 +503,10 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
                 K[64 + lane] = make_uint4(pack_bf16x2(kv[8], kv[9]), pack_bf16x2(kv[10], kv[11]),
                                           pack_bf16x2(kv[12], kv[13]), pack_bf16x2(kv[14], kv[15]));
             }
+            a0 = n0;
+            a1 = n1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) alv[i] = aln[i];
         }
         // partial means per (wave, half-wave) for each group's sample
 #pragma unroll
@@ -502,14 +577,25 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     int nit = 0;
     for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair<NW>(w, i) + 2;   // even
     const int r0 = (rotate && npairs > 0) ? (int)((unsigned)blk % (unsigned)npairs) : 0;
+    uint64_t plist = 0;   // this wave's pairs in visiting order (see Cursor)
+    for (int n = 0; n < npairs; ++n) {
+        int i = rev ? r0 - 1 - n : r0 + n;
+        i %= npairs;
+        if (i < 0) i += npairs;
+        plist |= (uint64_t)wave_pair<NW>(w, i) << (8 * n);
+    }
+    const WRsrc<PREC> wrs = w_rsrc<PREC>(g, o);
+    const int voff = 16 * lane;
 
     const unsigned char *kgrp[G];
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
-    // register ring of two iterations (two W blocks each); the k operand of
-    // iteration i sits in kb[i % 2], loaded one iteration ahead
-    WBlock<PREC> ring[2][2];
-    KOp<PREC> kb[2][G];
+    // register ring of D iterations (two W blocks each), refilled D iterations
+    // ahead; the k operand of an iteration is read from LDS one iteration ahead
+    // into its own ring slot
+    constexpr int D = walk_depth<PREC, G>();
+    WBlock<PREC> ring[D][2];
+    KOp<PREC> kb[D][G];
     v16f acc[2][G];
     float sq[G];
 #pragma unroll
@@ -522,62 +608,68 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     Cursor pc, mc;   // prefetch and compute cursors
     int last_b0 = 0;
     if (nit > 0) {
-        cursor_start<NW>(pc, w, npairs, r0, rev);
-        cursor_start<NW>(mc, w, npairs, r0, rev);
+        cursor_start(pc, plist, rev);
+        cursor_start(mc, plist, rev);
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int b0 = pair_block(pc);
-            last_b0 = b0;
-            load_wblock<PREC>(ring[r][0], g, o, pair_zero(pc) ? b0 + 1 : b0, lane);
-            load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-            cursor_next<NW>(pc, w, npairs, r0, rev);
+        for (int r = 0; r < D; ++r) {
+            const bool live = r < nit;
+            const int b0 = live ? pair_block(pc) : last_b0;
+            if (live) last_b0 = b0;
+            const bool z = live && pair_zero(pc);
+            load_wblock_rs<PREC>(ring[r][0], wrs, z ? b0 + 1 : b0, voff);
+            load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
+            if (live) cursor_next(pc, plist, rev);
         }
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
     }
-    for (int base = 0; base < nit; base += 2) {
+    for (int base = 0; base < nit; base += D) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < D; ++r) {
             // this iteration's products; a pair's first iteration starts from zero, and
-            // the block above the diagonal (zero) is neither loaded nor multiplied
+            // the block above the diagonal (zero) is not multiplied
+            const bool act = base + r < nit;
             const bool zt = pair_zero(mc);
-            if (pair_start) {
-                if (zt) {
+            if (act) {
+                if (pair_start) {
+                    if (zt) {
 #pragma unroll
-                    for (int gg = 0; gg < G; ++gg) acc[0][gg] = v16f{};
+                        for (int gg = 0; gg < G; ++gg) acc[0][gg] = v16f{};
+                    } else {
+#pragma unroll
+                        for (int gg = 0; gg < G; ++gg) acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
+                    }
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
                 } else {
+                    if (!zt) {
 #pragma unroll
-                    for (int gg = 0; gg < G; ++gg) acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
+                        for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
+                    }
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
                 }
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
-            } else {
-                if (!zt) {
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
-                }
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
             }
-            // refill this ring slot two iterations ahead, the other k slot one ahead.
-            // Every iteration issues the same loads (past the end and in place of the
-            // zero block they repeat a block already fetched), so the memory counters
-            // stay exact and the wait before each product is for its own operands only.
+            // refill this ring slot D iterations ahead and read the next k operand.
+            // Every pass issues the same loads (past the end and in place of the zero
+            // block they repeat a block already fetched), so the memory counters stay
+            // exact and the wait before each product is for its own operands only.
             {
-                const bool live = base + r + 2 < nit;
+                const bool live = base + r + D < nit;
                 const int b0 = live ? pair_block(pc) : last_b0;
+                if (live) last_b0 = b0;
                 const bool z = live && pair_zero(pc);
-                load_wblock<PREC>(ring[r][0], g, o, z ? b0 + 1 : b0, lane);
-                load_wblock<PREC>(ring[r][1], g, o, b0 + 1, lane);
-                if (live) cursor_next<NW>(pc, w, npairs, r0, rev);
+                load_wblock_rs<PREC>(ring[r][0], wrs, z ? b0 + 1 : b0, voff);
+                load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
+                if (live) cursor_next(pc, plist, rev);
             }
-            const bool pair_end = cursor_next<NW>(mc, w, npairs, r0, rev);
+            const bool pair_end = act && cursor_next(mc, plist, rev);
             {
                 const int kit = base + r + 1 < nit ? mc.it : 0;
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], kit, lane, Mpad);
+                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[(r + 1) % D][gg], kgrp[gg], kit, lane, Mpad);
             }
-            pair_start = pair_end;
+            if (act) pair_start = pair_end;
             if (pair_end) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) {
