@@ -53,26 +53,6 @@ struct KOp<GPMPPI_BF16X3> {
     uint4 l[2];
 };
 
-template <int PREC>
-__device__ __forceinline__ void load_wblock(WBlock<PREC> &b, const GpDev &g, int o, int blk, int lane) {
-    if constexpr (PREC == GPMPPI_FP32) {
-        const float4 *p = g.w32 + o * g.w32_stride + (size_t)blk * 256 + lane;
-        b.v[0] = p[0];
-        b.v[1] = p[64];
-        b.v[2] = p[128];
-        b.v[3] = p[192];
-    } else {
-        const uint4 *p = g.wbh + o * g.wb_stride + (size_t)blk * 128 + lane;
-        b.h[0] = p[0];
-        b.h[1] = p[64];
-        if constexpr (PREC == GPMPPI_BF16X3) {
-            const uint4 *q = g.wbl + o * g.wb_stride + (size_t)blk * 128 + lane;
-            b.l[0] = q[0];
-            b.l[1] = q[64];
-        }
-    }
-}
-
 // Byte size of one sample group's k operand in LDS.
 template <int PREC>
 __host__ __device__ constexpr size_t kgroup_bytes(int Mpad) {
@@ -127,42 +107,6 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
     }
 }
 
-// Depth of the walk's W register ring (iterations in flight).  Two keep the
-// matrix cores fed on gfx950; three measured no faster for the BF16 form.
-template <int PREC, int G>
-__host__ __device__ constexpr int walk_depth() { return 2; }
-
-// The products of a pair's first iteration, accumulated onto zero.
-template <int PREC>
-__device__ __forceinline__ v16f mma_first(const WBlock<PREC> &b, const KOp<PREC> &k) {
-    v16f acc;
-    if constexpr (PREC == GPMPPI_FP32) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].x, k.v[0].x, v16f{}, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].y, k.v[0].y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].z, k.v[0].z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[0].w, k.v[0].w, acc, 0, 0, 0);
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].x, k.v[q].x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].y, k.v[q].y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].z, k.v[q].z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b.v[q].w, k.v[q].w, acc, 0, 0, 0);
-        }
-    } else {
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[0]), as_bf(k.h[0]), v16f{}, 0, 0, 0);
-        if constexpr (PREC == GPMPPI_BF16X3) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[0]), as_bf(k.l[0]), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[0]), as_bf(k.h[0]), acc, 0, 0, 0);
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[1]), as_bf(k.h[1]), acc, 0, 0, 0);
-        if constexpr (PREC == GPMPPI_BF16X3) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.h[1]), as_bf(k.l[1]), acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(b.l[1]), as_bf(k.h[1]), acc, 0, 0, 0);
-        }
-    }
-    return acc;
-}
-
 // Pair list of wave w of NW: round i holds pairs NW i .. NW i + NW - 1,
 // assigned in snake order so that the summed pair lengths (2u + 2) balance
 // across waves.
@@ -182,27 +126,30 @@ struct Cursor {
     int base;   // packed index of block (2u, 0): 2 u (u + 1)
 };
 
-__device__ __forceinline__ void cursor_pair(Cursor &c, uint64_t plist, bool rev) {
+template <bool REV>
+__device__ __forceinline__ void cursor_pair(Cursor &c, uint64_t plist) {
     const int u = (int)((plist >> (8 * (c.n & 7))) & 0xFFu);
     c.last = 2 * u + 1;
     c.base = 2 * u * (u + 1);
-    c.it = rev ? c.last : 0;
+    c.it = REV ? c.last : 0;
 }
 
-__device__ __forceinline__ void cursor_start(Cursor &c, uint64_t plist, bool rev) {
+template <bool REV>
+__device__ __forceinline__ void cursor_start(Cursor &c, uint64_t plist) {
     c.n = 0;
-    cursor_pair(c, plist, rev);
+    cursor_pair<REV>(c, plist);
 }
 
 // Advances; returns true when the iteration just left closed its pair.
-__device__ __forceinline__ bool cursor_next(Cursor &c, uint64_t plist, bool rev) {
-    if (!rev) {
-        if (++c.it <= c.last) return false;
+template <bool REV>
+__device__ __forceinline__ bool cursor_next(Cursor &c, uint64_t plist) {
+    if (!REV) {
+        if (__builtin_expect(++c.it <= c.last, 1)) return false;
     } else {
-        if (--c.it >= 0) return false;
+        if (__builtin_expect(--c.it >= 0, 1)) return false;
     }
     ++c.n;
-    cursor_pair(c, plist, rev);
+    cursor_pair<REV>(c, plist);
     return true;
 }
 
@@ -387,6 +334,75 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
     uint32_t r;
     __builtin_memcpy(&r, &h, 4);
     return r;
+}
+
+// The wave's share of |W k|^2 for the G sample groups: nit iterations over its
+// pairs (plist, see Cursor) in direction REV.  W streams from L2 through a
+// register ring two iterations deep, the k operand of the next iteration is
+// read from LDS one iteration ahead.  Every iteration issues the same loads:
+// past the end the cursors run into pair 0 of the padded list, and in place
+// of the zero block above the diagonal the diagonal block is fetched twice, so
+// the memory counters stay exact and each product waits for its own operands
+// only.  Accumulators start from zero and are cleared after each pair.
+template <int PREC, int G, bool REV>
+__device__ __forceinline__ void walk_pairs(const WRsrc<PREC> &wrs, int voff, const unsigned char *lds, int lane,
+                                           int Mpad, uint64_t plist, int nit, float sq[G]) {
+    const unsigned char *kgrp[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
+    WBlock<PREC> ring[2][2];
+    KOp<PREC> kb[2][G];
+    v16f acc[2][G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        acc[0][gg] = v16f{};
+        acc[1][gg] = v16f{};
+        sq[gg] = 0.0f;
+    }
+    Cursor pc, mc;   // prefetch and compute cursors
+    cursor_start<REV>(pc, plist);
+    cursor_start<REV>(mc, plist);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int b0 = pair_block(pc);
+        load_wblock_rs<PREC>(ring[r][0], wrs, pair_zero(pc) ? b0 + 1 : b0, voff);
+        load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
+        cursor_next<REV>(pc, plist);
+    }
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
+    for (int base = 0; base < nit; base += 2) {   // nit is even
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (!pair_zero(mc)) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
+            }
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
+            {   // refill this slot two iterations ahead
+                const int b0 = pair_block(pc);
+                load_wblock_rs<PREC>(ring[r][0], wrs, pair_zero(pc) ? b0 + 1 : b0, voff);
+                load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
+                cursor_next<REV>(pc, plist);
+            }
+            const bool pair_end = cursor_next<REV>(mc, plist);
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], mc.it, lane, Mpad);
+            if (__builtin_expect(pair_end, 0)) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        sq[gg] = fmaf(acc[0][gg][e], acc[0][gg][e], sq[gg]);
+                        sq[gg] = fmaf(acc[1][gg][e], acc[1][gg][e], sq[gg]);
+                    }
+                    acc[0][gg] = v16f{};
+                    acc[1][gg] = v16f{};
+                }
+            }
+        }
+    }
 }
 
 // One GP output for the B samples of the block; called by all threads with
@@ -587,101 +603,11 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     const WRsrc<PREC> wrs = w_rsrc<PREC>(g, o);
     const int voff = 16 * lane;
 
-    const unsigned char *kgrp[G];
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
-    // register ring of D iterations (two W blocks each), refilled D iterations
-    // ahead; the k operand of an iteration is read from LDS one iteration ahead
-    // into its own ring slot
-    constexpr int D = walk_depth<PREC, G>();
-    WBlock<PREC> ring[D][2];
-    KOp<PREC> kb[D][G];
-    v16f acc[2][G];
     float sq[G];
-#pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-        acc[0][gg] = v16f{};
-        acc[1][gg] = v16f{};
-        sq[gg] = 0.0f;
-    }
-    bool pair_start = true;
-    Cursor pc, mc;   // prefetch and compute cursors
-    int last_b0 = 0;
-    if (nit > 0) {
-        cursor_start(pc, plist, rev);
-        cursor_start(mc, plist, rev);
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            const bool live = r < nit;
-            const int b0 = live ? pair_block(pc) : last_b0;
-            if (live) last_b0 = b0;
-            const bool z = live && pair_zero(pc);
-            load_wblock_rs<PREC>(ring[r][0], wrs, z ? b0 + 1 : b0, voff);
-            load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
-            if (live) cursor_next(pc, plist, rev);
-        }
-#pragma unroll
-        for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
-    }
-    for (int base = 0; base < nit; base += D) {
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            // this iteration's products; a pair's first iteration starts from zero, and
-            // the block above the diagonal (zero) is not multiplied
-            const bool act = base + r < nit;
-            const bool zt = pair_zero(mc);
-            if (act) {
-                if (pair_start) {
-                    if (zt) {
-#pragma unroll
-                        for (int gg = 0; gg < G; ++gg) acc[0][gg] = v16f{};
-                    } else {
-#pragma unroll
-                        for (int gg = 0; gg < G; ++gg) acc[0][gg] = mma_first<PREC>(ring[r][0], kb[r][gg]);
-                    }
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) acc[1][gg] = mma_first<PREC>(ring[r][1], kb[r][gg]);
-                } else {
-                    if (!zt) {
-#pragma unroll
-                        for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
-                    }
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
-                }
-            }
-            // refill this ring slot D iterations ahead and read the next k operand.
-            // Every pass issues the same loads (past the end and in place of the zero
-            // block they repeat a block already fetched), so the memory counters stay
-            // exact and the wait before each product is for its own operands only.
-            {
-                const bool live = base + r + D < nit;
-                const int b0 = live ? pair_block(pc) : last_b0;
-                if (live) last_b0 = b0;
-                const bool z = live && pair_zero(pc);
-                load_wblock_rs<PREC>(ring[r][0], wrs, z ? b0 + 1 : b0, voff);
-                load_wblock_rs<PREC>(ring[r][1], wrs, b0 + 1, voff);
-                if (live) cursor_next(pc, plist, rev);
-            }
-            const bool pair_end = act && cursor_next(mc, plist, rev);
-            {
-                const int kit = base + r + 1 < nit ? mc.it : 0;
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[(r + 1) % D][gg], kgrp[gg], kit, lane, Mpad);
-            }
-            if (act) pair_start = pair_end;
-            if (pair_end) {
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        sq[gg] = fmaf(acc[0][gg][e], acc[0][gg][e], sq[gg]);
-                        sq[gg] = fmaf(acc[1][gg][e], acc[1][gg][e], sq[gg]);
-                    }
-                }
-            }
-        }
-    }
+    if (rev)
+        walk_pairs<PREC, G, true>(wrs, voff, lds, lane, Mpad, plist, nit, sq);
+    else
+        walk_pairs<PREC, G, false>(wrs, voff, lds, lane, Mpad, plist, nit, sq);
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) {
         sq[gg] += shfl_xor(sq[gg], 32);
