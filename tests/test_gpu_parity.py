@@ -369,7 +369,8 @@ def test_terrain_means_feed_the_weight_estimate():
 
 def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
     t = torch()
-    pr = W.make_config(0, K=300, T=12)
+    # M = 300: 10 row tiles in 5 row-tile pairs, so that the walk's start rotation matters
+    pr = W.make_config(0, K=300, T=12, M=300, N=300)
     S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
     ctx = B.gpmppi_init(pr, B.FP32)
     for groups in (1, 2):
@@ -377,7 +378,7 @@ def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
             for waves in (4, 8):
                 B.gpmppi_set_tuning(ctx, groups, rotate, waves)
                 got = B.gpmppi_get_tuning(ctx)
-                assert (got["groups"], got["waves"]) == (groups, waves)
+                assert (got["groups"], got["rotate"], got["waves"]) == (groups, rotate, waves)
                 S_g, tr_g = gpu_rollout(pr, ctx=ctx)
                 _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"shape groups={groups} rotate={rotate} waves={waves}")
                 S_g2, _ = gpu_rollout(pr, ctx=ctx)
