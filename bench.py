@@ -214,7 +214,7 @@ def main():
         costs = torch.empty(K, **f32)
         weights = torch.empty(K, **f32)
         stream = torch.cuda.current_stream()
-        shape = B.gpmppi_get_tuning(ctx) if args.no_tune else B.gpmppi_tune(ctx, x0, U, pr.seed, 2, stream)
+        shape = B.gpmppi_get_tuning(ctx) if args.no_tune else B.gpmppi_tune(ctx, x0, U, pr.seed, 5, stream)
         log(f"[bench] form={name} shape={shape} warmup={args.warmup}")
         for _ in range(args.warmup):
             B.gpmppi_rollout(ctx, x0, U, pr.seed, costs, None, stream)

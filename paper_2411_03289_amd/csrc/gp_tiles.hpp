@@ -236,11 +236,11 @@ struct Shapes {
 template <int G>
 __host__ __device__ constexpr bool scalar_inputs() { return G == 2; }
 
-// The BF16 form computes the kernel-vector exponents on the matrix cores from
-// prepacked point operands (GpDev::zop) and needs only alpha of both outputs
-// in LDS, staged once per launch.
+// The BF16 forms compute the kernel-vector exponents on the matrix cores from
+// prepacked point operands (GpDev::zop) and need only alpha of both outputs in
+// LDS, staged once per launch.
 template <int PREC>
-__host__ __device__ constexpr bool mfma_gen() { return PREC == GPMPPI_BF16; }
+__host__ __device__ constexpr bool mfma_gen() { return PREC != GPMPPI_FP32; }
 
 // Dynamic LDS layout: [G k-operand groups] then alpha [2][Mpad] (BF16 form),
 // nothing (scalar-cache inputs) or the per-point inputs of one output.
@@ -514,10 +514,22 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
 #pragma unroll
                 for (int r = 0; r < 16; ++r) ms[gg] = fmaf(kv[r], alv[r >> 2][r & 3], ms[gg]);
                 uint4 *K = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad)) + (size_t)jt * 128;
-                K[lane] = make_uint4(pack_bf16x2(kv[0], kv[1]), pack_bf16x2(kv[2], kv[3]), pack_bf16x2(kv[4], kv[5]),
-                                     pack_bf16x2(kv[6], kv[7]));
-                K[64 + lane] = make_uint4(pack_bf16x2(kv[8], kv[9]), pack_bf16x2(kv[10], kv[11]),
-                                          pack_bf16x2(kv[12], kv[13]), pack_bf16x2(kv[14], kv[15]));
+                uint32_t hv[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) hv[i] = pack_bf16x2(kv[2 * i], kv[2 * i + 1]);
+                K[lane] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+                K[64 + lane] = make_uint4(hv[4], hv[5], hv[6], hv[7]);
+                if constexpr (PREC == GPMPPI_BF16X3) {   // the BF16 remainders k - hi for the split products
+                    uint32_t lv[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        lv[i] = pack_bf16x2(kv[2 * i] - bf16_to_f32((uint16_t)hv[i]),
+                                            kv[2 * i + 1] - bf16_to_f32((uint16_t)(hv[i] >> 16)));
+                    uint4 *L = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad) + (size_t)Mpad * 64) +
+                               (size_t)jt * 128;
+                    L[lane] = make_uint4(lv[0], lv[1], lv[2], lv[3]);
+                    L[64 + lane] = make_uint4(lv[4], lv[5], lv[6], lv[7]);
+                }
             }
             a0 = n0;
             a1 = n1;
