@@ -97,6 +97,54 @@ def test_gp_predict_bf16_forms():
             assert np.all(gv[o] >= g.sn2 * (1 - 1e-6))
 
 
+@pytest.mark.parametrize("M", [1, 50, 77, 300, 520])
+def test_gp_predict_bf16_forms_ragged(M):
+    """The BF16 forms' kernel vectors (exponents on the matrix cores from three-term BF16 splits)
+    at sizes whose column tiles do not divide evenly between the waves: the mean keeps the FP32
+    bound, the variance the form's."""
+    pr, q = _gp_case(M, seed=5)
+    gps = G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)
+    for prec, vtol in ((B.BF16X3, 2e-5), (B.BF16, 2e-2)):
+        gm, gv = _gpu_predict(pr, q, prec)
+        for o, g in enumerate(gps):
+            m, _, v = g.predict(q)
+            absdot = np.abs(G.se_ard(q, g.Z, g.log_ell, g.log_sf)) @ np.abs(g.alpha)
+            em = np.abs(gm[o] - m)
+            _print(f"gp M={M} form={prec} o={o}", mean_err=em.max(), var_err=np.abs(gv[o] - v).max())
+            assert np.all(em <= 1e-5 + 8 * EPS32 * absdot)
+            assert np.abs(gv[o] - v).max() <= vtol
+            assert np.all(gv[o] >= g.sn2 * (1 - 1e-6))
+
+
+@pytest.mark.parametrize("prec", [B.BF16X3, B.BF16])
+def test_bf16_rollout_states_at_every_shape(prec):
+    """BF16-form rollouts at M = 300 (ten column tiles over four or eight waves) for every launch
+    shape: the state trajectory depends on the GP mean only, which stays FP32 in these forms, so
+    states, controls and means follow the oracle at the FP32 bar; the variance meets the form's."""
+    pr = W.small_problem(K=150, T=10, M=300, n_obs=7, path="eight", seed_data=26, U_scale=1.0)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    vtol = 5e-5 if prec == B.BF16X3 else 2e-2
+    # FP32 dot-product bound of each step's GP mean: sum_j |k_j alpha_j| at the oracle's inputs
+    q = np.concatenate([tr_o.x[:-1, :, 3:5], tr_o.u], axis=2).reshape(-1, 4)
+    absdot = np.stack([np.abs(G.se_ard(q, g.Z, g.log_ell, g.log_sf)) @ np.abs(g.alpha)
+                       for g in G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)], axis=1)
+    absdot = absdot.reshape(pr.T, pr.K, 2)
+    ctx = B.gpmppi_init(pr, prec)
+    for groups in (1, 2):
+        for waves in (4, 8):
+            B.gpmppi_set_tuning(ctx, groups, 1, waves)
+            S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+            ex = rel_err(tr_g["x"], tr_o.x, 1.0)
+            em = np.abs(tr_g["gp_mean"] - tr_o.gp_mean)
+            ev = np.abs(tr_g["gp_var"] - tr_o.gp_var)
+            _print(f"form={prec} groups={groups} waves={waves}", x=ex.max(), gp_mean=em.max(), gp_var=ev.max())
+            assert np.all(ex <= TOL), "states"
+            assert np.all(np.abs(tr_g["u"] - tr_o.u) <= 1e-5), "sampled controls"
+            assert np.all(em <= 1e-5 + 8 * EPS32 * absdot), "gp mean"
+            assert ev.max() <= vtol, "gp variance"
+            assert np.all(np.isfinite(S_g))
+
+
 def test_not_positive_definite_is_reported():
     pr = W.small_problem(M=8, seed_data=1)
     pr.Z[0, 1] = pr.Z[0, 0]
