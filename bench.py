@@ -65,10 +65,45 @@ def cpu_baseline(pr, n_samples):
     mppi.update(w, tr.u)
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return {"value": n_samples * pr.T / dt, "unit": "sample-steps/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"samples 0..{n_samples - 1} of K={pr.K}, full horizon T={pr.T}, M={pr.M}, "
-                      f"FP64 NumPy/SciPy, {dt:.1f} s wall"}
+    summary = {"value": n_samples * pr.T / dt, "unit": "sample-steps/s", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"samples 0..{n_samples - 1} of K={pr.K}, full horizon T={pr.T}, M={pr.M}, "
+                         f"FP64 NumPy/SciPy, {dt:.1f} s wall"}
+    return summary, tr
+
+
+def form_errors(B, torch, pr, tr, forms):
+    """Max-abs errors of each form against the FP64 oracle on the oracle's samples (0 .. n-1):
+    GP mean and predictive variance at the oracle's own queries (gpmppi_gp_predict), and the
+    lane margin r_bar - d_lane and least obstacle margin min_j d_bar_j of the form's rollout."""
+    import numpy as np
+    f32 = dict(device="cuda", dtype=torch.float32)
+    T, n = pr.T, tr.x.shape[1]
+    q = np.concatenate([tr.x[:-1, :, 3:5], tr.u], axis=2).reshape(-1, 4)   # [T][n] queries
+    fin = np.isfinite(tr.obs_margin)
+    out = {}
+    for name in forms:
+        ctx = B.gpmppi_init(pr, FORMS[name])
+        mean = torch.empty(2 * len(q), **f32)
+        var = torch.empty(2 * len(q), **f32)
+        B.gpmppi_gp_predict(ctx, torch.tensor(q, **f32), mean, var)
+        lm = torch.empty(T * pr.K, **f32)
+        om = torch.empty(T * pr.K, **f32)
+        B.gpmppi_rollout(ctx, torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32), pr.seed,
+                         torch.empty(pr.K, **f32), {"lane_margin_d": lm, "obs_margin_d": om})
+        torch.cuda.synchronize()
+        gm = mean.cpu().numpy().astype(np.float64).reshape(2, T, n)
+        gv = var.cpu().numpy().astype(np.float64).reshape(2, T, n)
+        lmg = lm.cpu().numpy().astype(np.float64).reshape(T, pr.K)[:, :n]
+        omg = om.cpu().numpy().astype(np.float64).reshape(T, pr.K)[:, :n]
+        out[name] = {
+            "gp_mean": float(max(np.abs(gm[o] - tr.gp_mean[:, :, o]).max() for o in range(2))),
+            "gp_var": float(max(np.abs(gv[o] - tr.gp_var[:, :, o]).max() for o in range(2))),
+            "lane_margin": float(np.abs(lmg - tr.lane_margin).max()),
+            "obs_margin": float(np.abs(omg[fin] - tr.obs_margin[fin]).max()) if fin.any() else 0.0,
+        }
+        del ctx
+    return out
 
 
 def extras(B, W, torch, log_fn):
@@ -276,7 +311,13 @@ def main():
         line["extras"] = extras(B, W, torch, log)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_samples} samples")
-        line["cpu_baseline"] = cpu_baseline(pr, args.cpu_samples)
+        line["cpu_baseline"], tr_o = cpu_baseline(pr, args.cpu_samples)
+        # errors of every form against the oracle on the same samples (outside the timed regions)
+        errs = form_errors(B, torch, pr, tr_o, list(results))
+        for name, e in errs.items():
+            results[name]["errors_vs_fp64"] = dict(e, U=results[name]["u_err_vs_fp64"],
+                                                   samples=f"0..{args.cpu_samples - 1}")
+            log(f"[bench] form={name} errors vs FP64 {results[name]['errors_vs_fp64']}")
     print(json.dumps(line), flush=True)
 
 
