@@ -226,6 +226,10 @@ struct Shapes {
     static constexpr int threads = 64 * NW;
     static constexpr int parts = NW * (2 / G);    // loop splitters: waves (x half-waves for G = 1)
     static constexpr int rparts = 2 * NW;         // partial sums per sample in the reduction arrays
+    // the waves that run the per-step geometry loops inside the variance contraction
+    // (with two waves per SIMD, the first four, which get the matrix core first and finish
+    // their share of W first)
+    static constexpr int lwaves = NW == 8 ? 4 : NW;
     static constexpr int stage_iters = (1536 + threads - 1) / threads;   // staged-input slots per thread
 };
 
@@ -405,14 +409,22 @@ __device__ __forceinline__ void walk_pairs(const WRsrc<PREC> &wrs, int voff, con
     }
 }
 
+struct NoSideWork {
+    __device__ void operator()(int) const {}
+};
+
 // One GP output for the B samples of the block; called by all threads with
 // the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
 // next_o replace them before returning (the caller synchronises before the
-// next use).  Returns the sample's GP mean and predictive variance.
-template <int PREC, int G, int NW = kWaves>
+// next use).  Returns the sample's GP mean and predictive variance.  side(w)
+// is called by every wave w once its share of the variance contraction is
+// done, before the workgroup synchronises: work that does not depend on this
+// output can fill the time the waves wait for each other there.
+template <int PREC, int G, int NW = kWaves, class Side = NoSideWork>
 __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
                                           bool rev, int rotate, int blk, unsigned char *lds, float *pred,
-                                          float *vred, float &mean_out, float &var_out) {
+                                          float *vred, float &mean_out, float &var_out,
+                                          const Side &side = Side()) {
     using S = Shapes<PREC, G, NW>;
     constexpr bool kScalar = scalar_inputs<G>();
     const int Mpad = g.Mpad;
@@ -625,6 +637,7 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
         sq[gg] += shfl_xor(sq[gg], 32);
         if (lane < 32) vred[w * S::B + gg * 32 + lane] = sq[gg];
     }
+    side(w);
     __syncthreads();
     if constexpr (!kScalar && !mfma_gen<PREC>()) {
         if (next_o >= 0) stage_store<PREC, NW>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));

@@ -1,27 +1,30 @@
 // K-sample x T-step rollout of the GP-augmented chance-constrained MPPI
 // controller on gfx950 (Alg. 1 Step 1 with Eqs. 1-3, 10, 11-16).
 //
-// Work decomposition: one workgroup of 256 threads (4 wave64s) owns
+// Work decomposition: one workgroup of NW wave64s (NW = 4 or 8) owns
 // B = 32 G samples (G = 1 or 2 column groups of the 32x32 matrix-core tiles).
 // Every wave keeps the state x (5) and covariance Sigma (15 symmetric entries)
 // of all B samples in registers for the whole horizon, lane l holding sample
-// l % B; the waves (and, for G = 1, the two half-waves) split the loops over
-// training points, polyline segments and obstacles between them.
+// l % B; the waves split the training points and the blocks of W between them.
 //
-// Per step and per GP output o:
-//  1. kernel vector: k_oj = exp2(c2_o - |q s_o - zs_oj|^2) for every sample and
-//     training point (VALU exp), the scaled inputs zs and alpha being read from
-//     LDS as broadcasts; k goes to LDS in the matrix-core operand layout and the
+// Per step:
+//  0. noise and sampled control; position, heading and A Sigma A^T, none of
+//     which needs the GP at this step (the GP variance reaches the position
+//     block of Sigma one step later).
+//  Per GP output o (gp_tiles.hpp):
+//  1. kernel vector k_oj = sf^2 exp(-|q - z_j|^2_ell / 2) for every sample and
+//     training point; k goes to LDS in the matrix-core operand layout and the
 //     GP mean k^T alpha is summed in FP32.
 //  2. variance: v = W k with W = L^-1 lower triangular, on the matrix cores:
-//     each wave walks its share of the 32x32 blocks (t, jt <= t) of W,
-//     streaming W from L2 through a register ring (distance D) while the k
-//     operand for the next block is read from LDS one block ahead; each W block
-//     serves G sample groups.  s2 = sn^2 + max(0, sf^2 - |v|^2).
-//     Odd steps walk outputs and blocks in reverse order, so that an L2 too
-//     small for both outputs' W still keeps most of it between steps.
-//  3. per-sample Euler step, covariance A Sigma A^T + dt^2 diag(0,0,0,s2),
-//     lane/obstacle tightening and the stage cost.
+//     each wave walks its share of the 32x32 blocks of W, streamed from L2
+//     through a register ring; each W block serves G sample groups.
+//     s2 = sn^2 + max(0, sf^2 - |v|^2).  Odd steps take the outputs and the
+//     blocks in reverse order, so the blocks walked last stay in L2 for the
+//     next step.  While the later waves finish their blocks, the first waves
+//     run the polyline (first output) and obstacle (second output) loops at
+//     x_{k+1}, Sigma_{k+1}.
+//  3. velocities with the GP mean, the GP variance into Sigma, lane/obstacle
+//     tightening and the stage cost.
 #include "gp_tiles.hpp"
 
 namespace gpmppi {
@@ -52,7 +55,6 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
     const int lane = tid & 63, w = tid >> 6;
     const int sl = lane % S::B;                     // sample within the block
     const int part = (G == 2) ? w : 2 * w + (lane >> 5);
-    const int wu = __builtin_amdgcn_readfirstlane(w);   // wave-uniform loop splitter for G = 2
     const int sg = blk * S::B + sl;
     const bool valid = sg < a.K;
     const bool writer = valid && w == 0 && lane < S::B;
@@ -102,57 +104,46 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         const bool rev = (k & 1) != 0;
         const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
         const float q[4] = {v, w_, u.x, u.y};
-        float m[2], s2[2];
-#pragma unroll
-        for (int oo = 0; oo < 2; ++oo) {
-            const int o = rev ? 1 - oo : oo;
-            __syncthreads();   // staged inputs visible; previous k-operand readers are done
-            const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
-                                 q[3] * a.gp.scale[o][3]};
-            gp_output<PREC, G, NW>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
-                               m[o], s2[o]);
-        }
 
-        // ---- mean: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2, 10)
+        // ---- the parts of the step that do not need the GP at step k: position and heading
+        // (Eqs. 1, 10) and the covariance propagation A Sigma A^T (Eq. 10); the GP variance
+        // enters Sigma_vv and Sigma_ww below, and reaches the position block one step later
         float sth, cth;
         sincosf(th, &sth, &cth);
         const float dt = dy.dt;
         const float a02 = -dt * v * sth, a03 = dt * cth, a12 = dt * v * cth, a13 = dt * sth, a24 = dt;
         const float a33 = dy.a33, a44 = dy.a44;
-        const float Xn = X + dt * v * cth;
-        const float Yn = Y + dt * v * sth;
-        const float thn = th + dt * w_;
-        const float vn = v + (dy.dt_tau_v * (u.x - v) + dt * m[0]);
-        const float wn = w_ + (dy.dt_tau_w * (u.y - w_) + dt * m[1]);
+        const float v_old = v, w_old = w_;
+        X = X + dt * v * cth;
+        Y = Y + dt * v * sth;
+        th = th + dt * w_;
+        {   // B = A Sigma (rows), then Sigma+_ij = sum_n B_in A_jn for i <= j
+            const float b00 = p00 + a02 * p02 + a03 * p03, b01 = p01 + a02 * p12 + a03 * p13,
+                        b02 = p02 + a02 * p22 + a03 * p23, b03 = p03 + a02 * p23 + a03 * p33,
+                        b04 = p04 + a02 * p24 + a03 * p34;
+            const float b11 = p11 + a12 * p12 + a13 * p13, b12 = p12 + a12 * p22 + a13 * p23,
+                        b13 = p13 + a12 * p23 + a13 * p33, b14 = p14 + a12 * p24 + a13 * p34;
+            const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
+            const float b33 = a33 * p33, b34 = a33 * p34;
+            const float b44 = a44 * p44;
+            p00 = b00 + a02 * b02 + a03 * b03;
+            p01 = b01 + a12 * b02 + a13 * b03;
+            p02 = b02 + a24 * b04;
+            p03 = a33 * b03;
+            p04 = a44 * b04;
+            p11 = b11 + a12 * b12 + a13 * b13;
+            p12 = b12 + a24 * b14;
+            p13 = a33 * b13;
+            p14 = a44 * b14;
+            p22 = b22 + a24 * b24;
+            p23 = a33 * b23;
+            p24 = a44 * b24;
+            p33 = a33 * b33;
+            p34 = a44 * b34;
+            p44 = a44 * b44;
+        }
 
-        // ---- covariance: Sigma+ = A Sigma A^T + dt^2 diag(0, 0, 0, s2_v, s2_w) (Eq. 10)
-        // B = A Sigma (rows), then Sigma+_ij = sum_n B_in A_jn for i <= j.
-        const float b00 = p00 + a02 * p02 + a03 * p03, b01 = p01 + a02 * p12 + a03 * p13,
-                    b02 = p02 + a02 * p22 + a03 * p23, b03 = p03 + a02 * p23 + a03 * p33,
-                    b04 = p04 + a02 * p24 + a03 * p34;
-        const float b11 = p11 + a12 * p12 + a13 * p13, b12 = p12 + a12 * p22 + a13 * p23,
-                    b13 = p13 + a12 * p23 + a13 * p33, b14 = p14 + a12 * p24 + a13 * p34;
-        const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
-        const float b33 = a33 * p33, b34 = a33 * p34;
-        const float b44 = a44 * p44;
-        p00 = b00 + a02 * b02 + a03 * b03;
-        p01 = b01 + a12 * b02 + a13 * b03;
-        p02 = b02 + a24 * b04;
-        p03 = a33 * b03;
-        p04 = a44 * b04;
-        p11 = b11 + a12 * b12 + a13 * b13;
-        p12 = b12 + a24 * b14;
-        p13 = a33 * b13;
-        p14 = a44 * b14;
-        p22 = b22 + a24 * b24;
-        p23 = a33 * b23;
-        p24 = a44 * b24;
-        p33 = a33 * b33 + dt * dt * s2[0];
-        p34 = a44 * b34;
-        p44 = a44 * b44 + dt * dt * s2[1];
-        X = Xn; Y = Yn; th = thn; v = vn; w_ = wn;
-
-        // ---- chance constraints at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16); with Step 2
+        // ---- chance-constraint geometry at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16); with Step 2
         // tightening the covariance is the nominal sequence's, shared by all samples
         float sa = p00, sb = p01, sc = p11;
         if (a.tight_sxy) {
@@ -162,56 +153,66 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         }
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
-        float best = INFINITY;   // squared distance to the polyline (this part's segments)
-        float om = INFINITY;     // least tightened obstacle distance (this part's obstacles)
-        if constexpr (G == 2) {
-            // wave-uniform indices: segments and obstacles come through the scalar cache
-            if (geo.path_kind != 0) {
+        // Loops over polyline segments (during the first output's contraction) and obstacles
+        // (during the second's), run by the first S::lwaves waves, which finish their share of
+        // W first: wave w's squared distance to segments w, w + lwaves, ... and least tightened
+        // distance to obstacles w, w + lwaves, ..., to ored[w] and ored[lwaves + w] (with one
+        // sample group both half-waves hold the same samples and write the same values).
+        const float Xs = X, Ys = Y;
+        auto loops = [&](int oo, int wv) {
+            if (wv >= S::lwaves) return;   // wave-uniform: segments and obstacles through the scalar cache
+            if (oo == 0) {
+                if (geo.path_kind == 0) return;
+                float best = INFINITY;
                 const const_v4p segs = (const_v4p)geo.seg;
                 const const_fp sinv = (const_fp)geo.seg_inv;
 #pragma unroll 4
-                for (int i = wu; i < geo.P; i += S::parts) {
+                for (int i = wv; i < geo.P; i += S::lwaves) {
                     const v4f sgm = segs[i];
-                    const float rx = X - sgm.x, ry = Y - sgm.y;
+                    const float rx = Xs - sgm.x, ry = Ys - sgm.y;
                     float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
                     t = fminf(fmaxf(t, 0.0f), 1.0f);
                     const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
                     best = fminf(best, ex * ex + ey * ey);
                 }
-            }
-            const const_v4p obs = (const_v4p)geo.obs;
+                ored[wv * S::B + sl] = best;
+            } else {
+                float om = INFINITY;
+                const const_v4p obs = (const_v4p)geo.obs;
 #pragma unroll 2
-            for (int j = wu; j < geo.n_obs; j += S::parts) {
-                const v4f ob = obs[j];
-                om = fminf(om, obstacle_margin(X - ob.x, Y - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
-            }
-        } else {
-            if (geo.path_kind != 0) {
-                for (int i = part; i < geo.P; i += S::parts) {
-                    const float4 sgm = geo.seg[i];
-                    const float rx = X - sgm.x, ry = Y - sgm.y;
-                    float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
-                    t = fminf(fmaxf(t, 0.0f), 1.0f);
-                    const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
-                    best = fminf(best, ex * ex + ey * ey);
+                for (int j = wv; j < geo.n_obs; j += S::lwaves) {
+                    const v4f ob = obs[j];
+                    om = fminf(om, obstacle_margin(Xs - ob.x, Ys - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
                 }
+                ored[(S::lwaves + wv) * S::B + sl] = om;
             }
-            for (int j = part; j < geo.n_obs; j += S::parts) {
-                const float4 ob = geo.obs[j];
-                om = fminf(om, obstacle_margin(X - ob.x, Y - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
-            }
-        }
-        __syncthreads();   // readers of the last output's partial sums are done
-        pred[part * S::B + sl] = best;
-        ored[part * S::B + sl] = om;
-        __syncthreads();
-        float best_all = INFINITY, om_all = INFINITY;
+        };
+
+        float m[2], s2[2];
 #pragma unroll
-        for (int p = 0; p < S::parts; ++p) {
-            best_all = fminf(best_all, pred[p * S::B + sl]);
-            om_all = fminf(om_all, ored[p * S::B + sl]);
+        for (int oo = 0; oo < 2; ++oo) {
+            const int o = rev ? 1 - oo : oo;
+            __syncthreads();   // staged inputs visible; previous k-operand readers are done
+            const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
+                                 q[3] * a.gp.scale[o][3]};
+            gp_output<PREC, G, NW>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
+                                   m[o], s2[o], [&](int wv) { loops(oo, wv); });
         }
-        om = om_all;
+
+        // ---- velocities: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2,
+        // 10), and the GP variance into the covariance (Eq. 10)
+        v = v_old + (dy.dt_tau_v * (u.x - v_old) + dt * m[0]);
+        w_ = w_old + (dy.dt_tau_w * (u.y - w_old) + dt * m[1]);
+        p33 += dt * dt * s2[0];
+        p44 += dt * dt * s2[1];
+
+        // the loop parts' partial results were written before the contraction's last barrier
+        float best_all = INFINITY, om = INFINITY;
+#pragma unroll
+        for (int p = 0; p < S::lwaves; ++p) {
+            if (geo.path_kind != 0) best_all = fminf(best_all, ored[p * S::B + sl]);
+            om = fminf(om, ored[(S::lwaves + p) * S::B + sl]);
+        }
         float dl;
         if (geo.path_kind == 0) {
             const float dx = X - geo.cx, dyy = Y - geo.cy;
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::rparts * S::B];
-    __shared__ float ored[S::parts * S::B];
+    __shared__ float ored[2 * S::lwaves * S::B];
     __shared__ float vred[NW * S::B];
     rollout_block<PREC, G, NW>(a, blockIdx.x, lds, pred, ored, vred);
 }
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(const RolloutArg
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::rparts * S::B];
-    __shared__ float ored[S::parts * S::B];
+    __shared__ float ored[2 * S::lwaves * S::B];
     __shared__ float vred[NW * S::B];
     __shared__ int next_item;
     for (;;) {
