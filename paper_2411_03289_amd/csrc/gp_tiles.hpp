@@ -113,6 +113,25 @@ __device__ __forceinline__ void mma_block(v16f &acc, const WBlock<PREC> &b, cons
 template <int NW>
 __device__ __forceinline__ int wave_pair(int w, int i) { return (i & 1) ? NW * i + NW - 1 - w : NW * i + w; }
 
+// Row-tile list of wave w of NW for the single-row walk.  With eight waves,
+// waves w and w + 4 share a SIMD and its matrix core, so the rows are dealt
+// per SIMD: round i gives SIMD s = w % 4 the rows 8i + s (its first wave) and
+// 8i + 7 - s (its second), which sum to the same block count on every SIMD.
+// Walk over W: row-tile pairs (2u, 2u + 1) of 2u + 2 iterations, dealt to the
+// waves in snake order, balance exactly when every wave takes an even number
+// of them; otherwise the walk goes by single row tiles t (t + 1 blocks).
+__host__ __device__ constexpr bool walk_by_rows(int NT, int NW) {
+    return ((NT >> 1) % NW) != 0 || (((NT >> 1) / NW) & 1) != 0;
+}
+// Walk kinds a kernel is built for: either, decided per call, or one of them.
+enum WalkKind { kWalkAny = 0, kWalkPairs = 1, kWalkRows = 2 };
+
+template <int NW>
+__device__ __forceinline__ int wave_row(int w, int i) {
+    if constexpr (NW == 8) return (w < 4) ? 8 * i + w : 8 * i + 11 - w;
+    else return wave_pair<NW>(w, i);
+}
+
 // Position in a wave's iteration sequence.  The wave's pairs, in visiting
 // order, are packed 8 bits each into plist (at most 8 pairs: Mpad <= 1024);
 // forward: pairs in order, it ascending; reverse: the exact reverse of that
@@ -156,6 +175,47 @@ __device__ __forceinline__ bool cursor_next(Cursor &c, uint64_t plist) {
 __device__ __forceinline__ int pair_block(const Cursor &c) { return c.base + 2 * c.it; }
 // The pair's last column tile: its block (2u, 2u + 1) lies above the diagonal.
 __device__ __forceinline__ bool pair_zero(const Cursor &c) { return c.it == c.last; }
+
+// Position in a wave's sequence of single row tiles t (blocks (t, 0) .. (t, t)),
+// packed 8 bits each into rlist in visiting order (at most 8 rows); forward:
+// columns ascending, reverse: the exact reverse sequence.  Past the end the
+// cursor runs into the padded entries (row 0, a valid block).
+struct RowCursor {
+    int n;      // rows completed
+    int c;      // current column tile
+    int t;      // current row tile
+    int base;   // packed index of block (t, 0): 2 u (u + 1) + t % 2 with u = t / 2
+};
+
+template <bool REV>
+__device__ __forceinline__ void rcursor_row(RowCursor &c, uint64_t rlist) {
+    const int t = (int)((rlist >> (8 * (c.n & 7))) & 0xFFu);
+    const int u = t >> 1;
+    c.t = t;
+    c.base = 2 * u * (u + 1) + (t & 1);
+    c.c = REV ? t : 0;
+}
+
+template <bool REV>
+__device__ __forceinline__ void rcursor_start(RowCursor &c, uint64_t rlist) {
+    c.n = 0;
+    rcursor_row<REV>(c, rlist);
+}
+
+// Advances; returns true when the iteration just left closed its row.
+template <bool REV>
+__device__ __forceinline__ bool rcursor_next(RowCursor &c, uint64_t rlist) {
+    if (!REV) {
+        if (__builtin_expect(++c.c <= c.t, 1)) return false;
+    } else {
+        if (__builtin_expect(--c.c >= 0, 1)) return false;
+    }
+    ++c.n;
+    rcursor_row<REV>(c, rlist);
+    return true;
+}
+
+__device__ __forceinline__ int row_block(const RowCursor &c) { return c.base + 2 * c.c; }
 
 // Buffer resources over one output's packed W: the block offset goes in the
 // scalar offset, the lane offset stays in one VGPR, out-of-range reads return 0.
@@ -413,6 +473,60 @@ struct NoSideWork {
     __device__ void operator()(int) const {}
 };
 
+// The wave's share of |W k|^2 by single row tiles (rlist, see RowCursor), nb
+// blocks in all: one block per iteration, W streamed through a register ring
+// four blocks deep, the k operand of the next block read from LDS one block
+// ahead.  Used where the row-tile pairs cannot be spread evenly over the
+// waves; every block loads its own k operand, twice the LDS reads of the pair
+// walk.  Iterations past nb (to a multiple of four) load but do not multiply.
+template <int PREC, int G, bool REV>
+__device__ __forceinline__ void walk_rows(const WRsrc<PREC> &wrs, int voff, const unsigned char *lds, int lane,
+                                          int Mpad, uint64_t rlist, int nb, float sq[G]) {
+    const unsigned char *kgrp[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
+    WBlock<PREC> ring[4];
+    KOp<PREC> kb[2][G];
+    v16f acc[G];
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        acc[gg] = v16f{};
+        sq[gg] = 0.0f;
+    }
+    RowCursor pc, mc;   // prefetch and compute cursors
+    rcursor_start<REV>(pc, rlist);
+    rcursor_start<REV>(mc, rlist);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        load_wblock_rs<PREC>(ring[r], wrs, row_block(pc), voff);
+        rcursor_next<REV>(pc, rlist);
+    }
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.c, lane, Mpad);
+    for (int base = 0; base < nb; base += 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (base + r < nb) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[gg], ring[r], kb[r & 1][gg]);
+            }
+            load_wblock_rs<PREC>(ring[r], wrs, row_block(pc), voff);   // four blocks ahead
+            rcursor_next<REV>(pc, rlist);
+            const bool row_end = rcursor_next<REV>(mc, rlist);
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[(r + 1) & 1][gg], kgrp[gg], mc.c, lane, Mpad);
+            if (__builtin_expect(row_end, 0)) {
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) sq[gg] = fmaf(acc[gg][e], acc[gg][e], sq[gg]);
+                    acc[gg] = v16f{};
+                }
+            }
+        }
+    }
+}
+
 // One GP output for the B samples of the block; called by all threads with
 // the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
 // next_o replace them before returning (the caller synchronises before the
@@ -420,7 +534,7 @@ struct NoSideWork {
 // is called by every wave w once its share of the variance contraction is
 // done, before the workgroup synchronises: work that does not depend on this
 // output can fill the time the waves wait for each other there.
-template <int PREC, int G, int NW = kWaves, class Side = NoSideWork>
+template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny, class Side = NoSideWork>
 __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
                                           bool rev, int rotate, int blk, unsigned char *lds, float *pred,
                                           float *vred, float &mean_out, float &var_out,
@@ -610,28 +724,43 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     // ---- variance contraction on the matrix cores
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int NP = g.NT >> 1;
-    const int rounds = (NP + NW - 1) / NW;
-    int npairs = rounds;
-    if (rounds > 0 && wave_pair<NW>(w, rounds - 1) >= NP) npairs = rounds - 1;
-    int nit = 0;
-    for (int i = 0; i < npairs; ++i) nit += 2 * wave_pair<NW>(w, i) + 2;   // even
-    const int r0 = (rotate && npairs > 0) ? (int)((unsigned)blk % (unsigned)npairs) : 0;
-    uint64_t plist = 0;   // this wave's pairs in visiting order (see Cursor)
-    for (int n = 0; n < npairs; ++n) {
+    // units of work: row-tile pairs (wave_pair) or single row tiles (wave_row)
+    const int NT = g.NT, NP = NT >> 1;
+    const bool by_rows = WALK == kWalkAny ? walk_by_rows(NT, NW) : WALK == kWalkRows;
+    const int nunit_all = by_rows ? NT : NP;
+    const int rounds = (nunit_all + NW - 1) / NW;
+    auto unit = [&](int i) { return by_rows ? wave_row<NW>(w, i) : wave_pair<NW>(w, i); };
+    int nunits = rounds;
+    if (rounds > 0 && unit(rounds - 1) >= nunit_all) nunits = rounds - 1;
+    int nwork = 0;   // pair walk: iterations (even); row walk: blocks
+    for (int i = 0; i < nunits; ++i) nwork += by_rows ? unit(i) + 1 : 2 * unit(i) + 2;
+    const int r0 = (rotate && nunits > 0) ? (int)((unsigned)blk % (unsigned)nunits) : 0;
+    uint64_t ulist = 0;   // this wave's units in visiting order (see Cursor, RowCursor)
+    for (int n = 0; n < nunits; ++n) {
         int i = rev ? r0 - 1 - n : r0 + n;
-        i %= npairs;
-        if (i < 0) i += npairs;
-        plist |= (uint64_t)wave_pair<NW>(w, i) << (8 * n);
+        i %= nunits;
+        if (i < 0) i += nunits;
+        ulist |= (uint64_t)unit(i) << (8 * n);
     }
     const WRsrc<PREC> wrs = w_rsrc<PREC>(g, o);
     const int voff = 16 * lane;
 
     float sq[G];
-    if (rev)
-        walk_pairs<PREC, G, true>(wrs, voff, lds, lane, Mpad, plist, nit, sq);
-    else
-        walk_pairs<PREC, G, false>(wrs, voff, lds, lane, Mpad, plist, nit, sq);
+    if (WALK != kWalkPairs && by_rows) {
+        if constexpr (WALK != kWalkPairs) {
+            if (rev)
+                walk_rows<PREC, G, true>(wrs, voff, lds, lane, Mpad, ulist, nwork, sq);
+            else
+                walk_rows<PREC, G, false>(wrs, voff, lds, lane, Mpad, ulist, nwork, sq);
+        }
+    } else {
+        if constexpr (WALK != kWalkRows) {
+            if (rev)
+                walk_pairs<PREC, G, true>(wrs, voff, lds, lane, Mpad, ulist, nwork, sq);
+            else
+                walk_pairs<PREC, G, false>(wrs, voff, lds, lane, Mpad, ulist, nwork, sq);
+        }
+    }
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) {
         sq[gg] += shfl_xor(sq[gg], 32);

@@ -47,7 +47,7 @@ __device__ __forceinline__ float obstacle_margin(float dx, float dy, float radiu
 
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
 // problem; called by all threads of a workgroup.
-template <int PREC, int G, int NW = kWaves>
+template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny>
 __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, unsigned char *lds, float *pred,
                                               float *ored, float *vred) {
     using S = Shapes<PREC, G, NW>;
@@ -195,8 +195,8 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
             __syncthreads();   // staged inputs visible; previous k-operand readers are done
             const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
                                  q[3] * a.gp.scale[o][3]};
-            gp_output<PREC, G, NW>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred, vred,
-                                   m[o], s2[o], [&](int wv) { loops(oo, wv); });
+            gp_output<PREC, G, NW, WALK>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred,
+                                         vred, m[o], s2[o], [&](int wv) { loops(oo, wv); });
         }
 
         // ---- velocities: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2,
@@ -282,14 +282,14 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
     if (writer) a.costs[sg] = S_;
 }
 
-template <int PREC, int G, int NW>
+template <int PREC, int G, int NW, int WALK>
 __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[2 * S::lwaves * S::B];
     __shared__ float vred[NW * S::B];
-    rollout_block<PREC, G, NW>(a, blockIdx.x, lds, pred, ored, vred);
+    rollout_block<PREC, G, NW, WALK>(a, blockIdx.x, lds, pred, ored, vred);
 }
 
 // Persistent rollout of many independent problems: every workgroup takes
@@ -382,14 +382,21 @@ static hipError_t set_lds(F *fn, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int PREC, int G, int NW>
-static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
+// One problem: the kernel carries only the walk over W that its size takes.
+template <int PREC, int G, int NW, int WALK>
+static hipError_t launch_rollout_w(const RolloutArgs &a, hipStream_t st) {
     const size_t lds = dyn_lds_bytes<PREC, G>(a.gp.Mpad);
-    hipError_t e = set_lds(rollout_kernel<PREC, G, NW>, lds);
+    hipError_t e = set_lds(rollout_kernel<PREC, G, NW, WALK>, lds);
     if (e != hipSuccess) return e;
     const dim3 grid((a.K + 32 * G - 1) / (32 * G));
-    hipLaunchKernelGGL((rollout_kernel<PREC, G, NW>), grid, dim3(64 * NW), lds, st, a);
+    hipLaunchKernelGGL((rollout_kernel<PREC, G, NW, WALK>), grid, dim3(64 * NW), lds, st, a);
     return hipGetLastError();
+}
+
+template <int PREC, int G, int NW>
+static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
+    return walk_by_rows(a.gp.NT, NW) ? launch_rollout_w<PREC, G, NW, kWalkRows>(a, st)
+                                     : launch_rollout_w<PREC, G, NW, kWalkPairs>(a, st);
 }
 
 template <int PREC>
