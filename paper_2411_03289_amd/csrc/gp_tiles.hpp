@@ -527,18 +527,108 @@ __device__ __forceinline__ void walk_rows(const WRsrc<PREC> &wrs, int voff, cons
     }
 }
 
-// One GP output for the B samples of the block; called by all threads with
-// the inputs of output o staged in LDS.  If next_o >= 0 the inputs of output
-// next_o replace them before returning (the caller synchronises before the
-// next use).  Returns the sample's GP mean and predictive variance.  side(w)
-// is called by every wave w once its share of the variance contraction is
-// done, before the workgroup synchronises: work that does not depend on this
-// output can fill the time the waves wait for each other there.
-template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny, class Side = NoSideWork>
-__device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
-                                          bool rev, int rotate, int blk, unsigned char *lds, float *pred,
-                                          float *vred, float &mean_out, float &var_out,
-                                          const Side &side = Side()) {
+// ---------------------------------------------------------------- matrix-core generation
+// The exponents c2 - |qs - zs_j|^2 of a 32-point column tile for 32 samples come
+// from two 32x32x16 BF16 products with the FP32 factors split into three BF16
+// terms (the operand layout is described at pack_zop_kernel); exp2, the mean and
+// the BF16 k operand on the VALU.  Lane l: sample 32 g + l % 32, points
+// 8 (l / 32) + r (r < 8) and 16 + 8 (l / 32) + r - 8 of the tile.
+
+// B operands (the samples' split factors) of the G groups for scaled queries qs.
+template <int G>
+__device__ __forceinline__ void gen_bop(const float qs[4], int hl, uint4 bop[G][2]) {
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        float qv[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const float other = (G == 2) ? shfl_xor(qs[d], 32) : qs[d];
+            qv[d] = (G == 1 || hl == gg) ? qs[d] : other;
+        }
+        const float qq = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
+        uint32_t qh[4], qm[4], ql[4], nqq[3];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) split3_bits(qv[d], qh[d], qm[d], ql[d]);
+        split3_bits(-qq, nqq[0], nqq[1], nqq[2]);
+        const uint32_t one = 0x3f80u;
+        if (hl == 0) {   // slots 0-7 of both products: (qh, qm) and (qm, qh)
+            bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, qm[0] | qm[1] << 16, qm[2] | qm[3] << 16);
+            bop[gg][1] = make_uint4(qm[0] | qm[1] << 16, qm[2] | qm[3] << 16, qh[0] | qh[1] << 16, qh[2] | qh[3] << 16);
+        } else {         // slots 8-15: (qh, ql) and (1, 1, 1, -qq h, -qq m, -qq l, 0, 0)
+            bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, ql[0] | ql[1] << 16, ql[2] | ql[3] << 16);
+            bop[gg][1] = make_uint4(one | one << 16, one | nqq[0] << 16, nqq[1] | nqq[2] << 16, 0u);
+        }
+    }
+}
+
+// A operands and alpha values of one column tile.
+struct GenOps {
+    uint4 a0, a1;
+    v4f al[4];
+};
+
+// Fetches tile jt (clamped to the last tile, so a fetch past the end repeats it).
+__device__ __forceinline__ void gen_fetch(GenOps &t, const uint4 *zop, const float *al, int NT, int jt, int lane,
+                                          int hl) {
+    const int jc = jt < NT ? jt : NT - 1;
+    t.a0 = zop[(jc * 2) * 64 + lane];
+    t.a1 = zop[(jc * 2 + 1) * 64 + lane];
+    const v4f *ap = reinterpret_cast<const v4f *>(al + 32 * jc + 8 * hl);
+    t.al[0] = ap[0];
+    t.al[1] = ap[1];
+    t.al[2] = ap[4];
+    t.al[3] = ap[5];
+}
+
+// One tile for the G groups: k = exp2 of the exponents, the mean partials ms, and
+// k packed to BF16 (hv) with, for the BF16x3 form, the BF16 remainders k - hi (lv).
+template <int PREC, int G>
+__device__ __forceinline__ void gen_tile(const GenOps &t, const uint4 bop[G][2], float ms[G], uint32_t hv[G][8],
+                                         uint32_t lv[G][8]) {
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        v16f e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(t.a0), as_bf(bop[gg][0]), v16f{}, 0, 0, 0);
+        e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(t.a1), as_bf(bop[gg][1]), e, 0, 0, 0);
+        float kv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) kv[r] = __builtin_amdgcn_exp2f(e[r]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ms[gg] = fmaf(kv[r], t.al[r >> 2][r & 3], ms[gg]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) hv[gg][i] = pack_bf16x2(kv[2 * i], kv[2 * i + 1]);
+        if constexpr (PREC == GPMPPI_BF16X3) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                lv[gg][i] = pack_bf16x2(kv[2 * i] - bf16_to_f32((uint16_t)hv[gg][i]),
+                                        kv[2 * i + 1] - bf16_to_f32((uint16_t)(hv[gg][i] >> 16)));
+        }
+    }
+}
+
+// Writes tile jt of the G groups' k operands to LDS.
+template <int PREC, int G>
+__device__ __forceinline__ void gen_store(unsigned char *lds, int Mpad, int jt, int lane, const uint32_t hv[G][8],
+                                          const uint32_t lv[G][8]) {
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        uint4 *K = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad)) + (size_t)jt * 128;
+        K[lane] = make_uint4(hv[gg][0], hv[gg][1], hv[gg][2], hv[gg][3]);
+        K[64 + lane] = make_uint4(hv[gg][4], hv[gg][5], hv[gg][6], hv[gg][7]);
+        if constexpr (PREC == GPMPPI_BF16X3) {
+            uint4 *L = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad) + (size_t)Mpad * 64) +
+                       (size_t)jt * 128;
+            L[lane] = make_uint4(lv[gg][0], lv[gg][1], lv[gg][2], lv[gg][3]);
+            L[64 + lane] = make_uint4(lv[gg][4], lv[gg][5], lv[gg][6], lv[gg][7]);
+        }
+    }
+}
+
+// Kernel vectors of output o for the B samples of the block and their GP mean;
+// called by all threads with the inputs of output o staged in LDS.  Ends with
+// a workgroup barrier; returns the sample's GP mean.
+template <int PREC, int G, int NW = kWaves>
+__device__ __forceinline__ float gp_gen(const GpDev &g, int o, const float qs[4], int part, int sl,
+                                        unsigned char *lds, float *pred) {
     using S = Shapes<PREC, G, NW>;
     constexpr bool kScalar = scalar_inputs<G>();
     const int Mpad = g.Mpad;
@@ -581,86 +671,28 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
             K[32 + s32] = make_float4(kv[1], kv[3], kv[5], kv[7]);
         }
     } else if constexpr (mfma_gen<PREC>()) {
-        // exponents on the matrix cores: two 32x32x16 BF16 products per 32-point column
-        // tile and sample group with the FP32 factors split into three BF16 terms (the
-        // operand layout is described at pack_zop_kernel); exp2, the mean and the BF16
-        // k operand on the VALU.  Lane l: sample 32 g + l % 32, points 8 (l / 32) + r
-        // (r < 8) and 16 + 8 (l / 32) + r - 8 of the tile.
         const int lane = threadIdx.x & 63, hl = lane >> 5;
         const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         const float *al = reinterpret_cast<const float *>(lds + G * kgroup_bytes<PREC>(Mpad)) + (size_t)o * Mpad;
         const uint4 *zop = g.zop + o * g.zop_stride;
         uint4 bop[G][2];
-#pragma unroll
-        for (int gg = 0; gg < G; ++gg) {
-            float qv[4];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const float other = (G == 2) ? shfl_xor(qs[d], 32) : qs[d];
-                qv[d] = (G == 1 || hl == gg) ? qs[d] : other;
-            }
-            const float qq = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
-            uint32_t qh[4], qm[4], ql[4], nqq[3];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) split3_bits(qv[d], qh[d], qm[d], ql[d]);
-            split3_bits(-qq, nqq[0], nqq[1], nqq[2]);
-            const uint32_t one = 0x3f80u;
-            if (hl == 0) {   // slots 0-7 of both products: (qh, qm) and (qm, qh)
-                bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, qm[0] | qm[1] << 16, qm[2] | qm[3] << 16);
-                bop[gg][1] = make_uint4(qm[0] | qm[1] << 16, qm[2] | qm[3] << 16, qh[0] | qh[1] << 16, qh[2] | qh[3] << 16);
-            } else {         // slots 8-15: (qh, ql) and (1, 1, 1, -qq h, -qq m, -qq l, 0, 0)
-                bop[gg][0] = make_uint4(qh[0] | qh[1] << 16, qh[2] | qh[3] << 16, ql[0] | ql[1] << 16, ql[2] | ql[3] << 16);
-                bop[gg][1] = make_uint4(one | one << 16, one | nqq[0] << 16, nqq[1] | nqq[2] << 16, 0u);
-            }
-        }
+        gen_bop<G>(qs, hl, bop);
         float ms[G];
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) ms[gg] = 0.0f;
-        // operands of this wave's tiles jt = wv, wv + NW, ..., each fetched one tile ahead
-        // (the fetch after the last tile repeats it, keeping the counters exact)
-        int jc = wv < g.NT ? wv : g.NT - 1;
-        uint4 a0 = zop[(jc * 2) * 64 + lane], a1 = zop[(jc * 2 + 1) * 64 + lane];
-        v4f alv[4];
-        {
-            const v4f *ap = reinterpret_cast<const v4f *>(al + 32 * jc + 8 * hl);
-            alv[0] = ap[0]; alv[1] = ap[1]; alv[2] = ap[4]; alv[3] = ap[5];
-        }
-        for (int jt = wv; jt < g.NT; jt += NW) {
-            const int jn = jt + NW < g.NT ? jt + NW : jt;
-            const uint4 n0 = zop[(jn * 2) * 64 + lane], n1 = zop[(jn * 2 + 1) * 64 + lane];
-            const v4f *apn = reinterpret_cast<const v4f *>(al + 32 * jn + 8 * hl);
-            const v4f aln[4] = {apn[0], apn[1], apn[4], apn[5]};
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                v16f e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a0), as_bf(bop[gg][0]), v16f{}, 0, 0, 0);
-                e = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a1), as_bf(bop[gg][1]), e, 0, 0, 0);
-                float kv[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) kv[r] = __builtin_amdgcn_exp2f(e[r]);
-#pragma unroll
-                for (int r = 0; r < 16; ++r) ms[gg] = fmaf(kv[r], alv[r >> 2][r & 3], ms[gg]);
-                uint4 *K = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad)) + (size_t)jt * 128;
-                uint32_t hv[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) hv[i] = pack_bf16x2(kv[2 * i], kv[2 * i + 1]);
-                K[lane] = make_uint4(hv[0], hv[1], hv[2], hv[3]);
-                K[64 + lane] = make_uint4(hv[4], hv[5], hv[6], hv[7]);
-                if constexpr (PREC == GPMPPI_BF16X3) {   // the BF16 remainders k - hi for the split products
-                    uint32_t lv[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        lv[i] = pack_bf16x2(kv[2 * i] - bf16_to_f32((uint16_t)hv[i]),
-                                            kv[2 * i + 1] - bf16_to_f32((uint16_t)(hv[i] >> 16)));
-                    uint4 *L = reinterpret_cast<uint4 *>(lds + gg * kgroup_bytes<PREC>(Mpad) + (size_t)Mpad * 64) +
-                               (size_t)jt * 128;
-                    L[lane] = make_uint4(lv[0], lv[1], lv[2], lv[3]);
-                    L[64 + lane] = make_uint4(lv[4], lv[5], lv[6], lv[7]);
-                }
-            }
-            a0 = n0;
-            a1 = n1;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) alv[i] = aln[i];
+        // this wave's tiles jt = wv, wv + NW, ..., each fetched one tile ahead into the
+        // other of two register sets
+        uint32_t hv[G][8], lv[G][8];
+        GenOps ta, tb;
+        gen_fetch(ta, zop, al, g.NT, wv, lane, hl);
+        for (int jt = wv; jt < g.NT; jt += 2 * NW) {
+            gen_fetch(tb, zop, al, g.NT, jt + NW, lane, hl);
+            gen_tile<PREC, G>(ta, bop, ms, hv, lv);
+            gen_store<PREC, G>(lds, Mpad, jt, lane, hv, lv);
+            if (jt + NW >= g.NT) break;
+            gen_fetch(ta, zop, al, g.NT, jt + 2 * NW, lane, hl);
+            gen_tile<PREC, G>(tb, bop, ms, hv, lv);
+            gen_store<PREC, G>(lds, Mpad, jt + NW, lane, hv, lv);
         }
         // partial means per (wave, half-wave) for each group's sample
 #pragma unroll
@@ -716,6 +748,26 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     // per-part partial means: the lanes of a part hold distinct samples
     if constexpr (!mfma_gen<PREC>()) pred[part * S::B + sl] = msum;
     __syncthreads();
+    float m = 0.0f;
+    constexpr int mparts = mfma_gen<PREC>() ? S::rparts : S::parts;
+#pragma unroll
+    for (int p = 0; p < mparts; ++p) m += pred[p * S::B + sl];
+    return m;
+}
+
+// Variance of output o for the B samples of the block, after gp_gen: v = W k on
+// the matrix cores, s2 = vscale (sn^2 + max(0, sf^2 - |v|^2)).  If next_o >= 0
+// the staged inputs of output next_o replace those of o (forms that stage them;
+// the caller synchronises before the next use).  side(w) is called by every
+// wave w once its share of the contraction is done, before the workgroup
+// synchronises: work that does not depend on this output can fill the time the
+// waves wait for each other there.  Ends with a workgroup barrier.
+template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny, class Side = NoSideWork>
+__device__ __forceinline__ float gp_walk(const GpDev &g, int o, int next_o, bool rev, int rotate, int blk,
+                                         unsigned char *lds, float *vred, int sl, const Side &side = Side()) {
+    using S = Shapes<PREC, G, NW>;
+    constexpr bool kScalar = scalar_inputs<G>();
+    const int Mpad = g.Mpad;
     StagedInputs st;
     if constexpr (!kScalar && !mfma_gen<PREC>()) {
         if (next_o >= 0) stage_load<PREC, NW>(st, g, next_o);
@@ -771,14 +823,20 @@ __device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, con
     if constexpr (!kScalar && !mfma_gen<PREC>()) {
         if (next_o >= 0) stage_store<PREC, NW>(st, g, lds, G * kgroup_bytes<PREC>(Mpad));
     }
-    float v2 = 0.0f, m = 0.0f;
+    float v2 = 0.0f;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) v2 += vred[ww * S::B + sl];
-    constexpr int mparts = mfma_gen<PREC>() ? S::rparts : S::parts;
-#pragma unroll
-    for (int p = 0; p < mparts; ++p) m += pred[p * S::B + sl];
-    var_out = g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));
-    mean_out = m;
+    return g.vscale[o] * (g.sn2[o] + fmaxf(0.0f, g.sf2[o] - v2));
+}
+
+// One GP output: gp_gen then gp_walk (see there).
+template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny, class Side = NoSideWork>
+__device__ __forceinline__ void gp_output(const GpDev &g, int o, int next_o, const float qs[4], int part, int sl,
+                                          bool rev, int rotate, int blk, unsigned char *lds, float *pred,
+                                          float *vred, float &mean_out, float &var_out,
+                                          const Side &side = Side()) {
+    mean_out = gp_gen<PREC, G, NW>(g, o, qs, part, sl, lds, pred);
+    var_out = gp_walk<PREC, G, NW, WALK>(g, o, next_o, rev, rotate, blk, lds, vred, sl, side);
 }
 
 }  // namespace gpmppi

@@ -195,14 +195,17 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
             __syncthreads();   // staged inputs visible; previous k-operand readers are done
             const float qs[4] = {q[0] * a.gp.scale[o][0], q[1] * a.gp.scale[o][1], q[2] * a.gp.scale[o][2],
                                  q[3] * a.gp.scale[o][3]};
-            gp_output<PREC, G, NW, WALK>(a.gp, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, a.rotate, blk, lds, pred,
-                                         vred, m[o], s2[o], [&](int wv) { loops(oo, wv); });
+            m[o] = gp_gen<PREC, G, NW>(a.gp, o, qs, part, sl, lds, pred);
+            s2[o] = gp_walk<PREC, G, NW, WALK>(a.gp, o, oo == 0 ? 1 - o : -1, rev, a.rotate, blk, lds, vred, sl,
+                                               [&](int wv) { loops(oo, wv); });
         }
 
         // ---- velocities: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2,
-        // 10), and the GP variance into the covariance (Eq. 10)
+        // 10)
         v = v_old + (dy.dt_tau_v * (u.x - v_old) + dt * m[0]);
         w_ = w_old + (dy.dt_tau_w * (u.y - w_old) + dt * m[1]);
+
+        // ---- the GP variance into the covariance (Eq. 10)
         p33 += dt * dt * s2[0];
         p44 += dt * dt * s2[1];
 
