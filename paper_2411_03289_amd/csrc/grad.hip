@@ -546,20 +546,37 @@ __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, con
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v16f{};
     const int col = lane & 31, rsel = lane >> 5;
-    for (long long n = n0; n < n1; n += 2) {
-        const long long row = n + rsel;
-        const bool ok = row < n1;
-        const float gv = ok ? Go[row] : 0.0f;
-        const float *rp = Ro + (size_t)(ok ? row : n0) * Mpad;
-        float av[2], bv[2];
+    // rows in chunks of kD row pairs: every load of a chunk is issued before its first
+    // product, so the loads' latency is paid once per chunk
+    constexpr int kD = 8;
+    for (long long n = n0; n < n1; n += 2 * kD) {
+        float gq[kD], ra[kD][2], rbq[kD][2];
+        bool okq[kD];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) av[i] = (vi[i] && ok) ? gv * rp[32 * (ti0 + i) + col] : 0.0f;
+        for (int q = 0; q < kD; ++q) {
+            const long long row = n + 2 * q + rsel;
+            okq[q] = row < n1;
+            const float *rp = Ro + (size_t)(okq[q] ? row : n0) * Mpad;
+            gq[q] = Go[okq[q] ? row : n0];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = (vj[j] && ok) ? rp[32 * (tj0 + j) + col] : 0.0f;
+            for (int i = 0; i < 2; ++i) ra[q][i] = vi[i] ? rp[32 * (ti0 + i) + col] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) rbq[q][j] = vj[j] ? rp[32 * (tj0 + j) + col] : 0.0f;
+        }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int q = 0; q < kD; ++q) {
+            const float gv = gq[q];
+            float av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = okq[q] ? gv * ra[q][i] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = okq[q] ? rbq[q][j] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
     }
     // epilogue: sum_ij P_ij dA_ij/dtheta over the wave's tiles (both triangles of a
     // diagonal block; off-diagonal blocks stand for their mirror image too)
