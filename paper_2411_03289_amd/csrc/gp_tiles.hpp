@@ -290,7 +290,7 @@ struct Shapes {
     // (with two waves per SIMD, the first four, which get the matrix core first and finish
     // their share of W first)
     static constexpr int lwaves = NW == 8 ? 4 : NW;
-    static constexpr int stage_iters = (1536 + threads - 1) / threads;   // staged-input slots per thread
+    static constexpr int stage_iters = (1280 + threads - 1) / threads;   // staged-input slots per thread
 };
 
 // Per-point GP inputs: with two sample groups a wave's chunks of training
@@ -323,16 +323,13 @@ __device__ __forceinline__ void stage_alpha(const GpDev &g, unsigned char *lds, 
     for (int i = threadIdx.x; i < g.Mpad / 2; i += 64 * NW) dst[i] = src[i];
 }
 
-// One GP output for the B samples of the block; called by all threads.
-// Returns the sample's GP mean and predictive variance.
-// Per-point inputs of output o staged in LDS (float4 slots):
-//   FP32:        zs [Mpad] then alpha [Mpad / 4]            (20 B per point)
-//   BF16 forms:  2 zs [Mpad] then (c2 - |zs|^2, alpha) [Mpad / 2]  (24 B per point)
-// held in registers between their global load and their store to LDS; thread
-// t of T owns slots t, t + T, ... (at most 1536 slots for Mpad <= 1024).
+// Per-point inputs of output o staged in LDS for the FP32 form with one sample
+// group (float4 slots): zs [Mpad] then alpha [Mpad / 4] (20 B per point), held in
+// registers between their global load and their store to LDS; thread t of T
+// owns slots t, t + T, ... (at most 1280 slots for Mpad <= 1024).
 template <int PREC>
 __host__ __device__ constexpr int staged_slots(int Mpad) {
-    return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : Mpad + (Mpad >> 1);
+    return PREC == GPMPPI_FP32 ? Mpad + (Mpad >> 2) : 0;
 }
 
 // Native vectors (not HIP's float4 struct, whose copies become memcpy of a
@@ -343,15 +340,10 @@ struct StagedInputs {
 
 template <int PREC, int NW = kWaves>
 __device__ __forceinline__ void stage_load(StagedInputs &st, const GpDev &g, int o) {
+    static_assert(PREC == GPMPPI_FP32, "only the FP32 form stages its per-point inputs");
     const int Mpad = g.Mpad, nz = Mpad, ns = staged_slots<PREC>(Mpad);
-    const v4f *zsrc, *asrc;
-    if constexpr (PREC == GPMPPI_FP32) {
-        zsrc = reinterpret_cast<const v4f *>(g.zs) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const v4f *>(g.alpha + (size_t)o * Mpad);
-    } else {
-        zsrc = reinterpret_cast<const v4f *>(g.zs2) + (size_t)o * Mpad;
-        asrc = reinterpret_cast<const v4f *>(g.cza + (size_t)o * Mpad * 2);
-    }
+    const v4f *zsrc = reinterpret_cast<const v4f *>(g.zs) + (size_t)o * Mpad;
+    const v4f *asrc = reinterpret_cast<const v4f *>(g.alpha + (size_t)o * Mpad);
 #pragma unroll
     for (int r = 0; r < Shapes<PREC, 1, NW>::stage_iters; ++r) {
         const int slot = threadIdx.x + r * (64 * NW);
@@ -697,53 +689,6 @@ __device__ __forceinline__ float gp_gen(const GpDev &g, int o, const float qs[4]
         // partial means per (wave, half-wave) for each group's sample
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) pred[(wv * 2 + hl) * S::B + 32 * gg + (lane & 31)] = ms[gg];
-    } else {
-        // expanded exponent: c2 - |zs|^2 - |q|^2 + q . (2 zs) = c2 - |q - zs|^2 <= c2 up to
-        // rounding, so exp2 needs no clamp; its FP32 rounding (~1e-6 relative in k)
-        // is far below the BF16 operand rounding (2^-9)
-        const v4f *cza = zs + Mpad;   // staged (c2 - |zs|^2, alpha) pairs
-        const const_v4p zsg = (const_v4p)g.zs2 + (size_t)o * Mpad;
-        const const_v4p czg = (const_v4p)(g.cza + (size_t)o * Mpad * 2);
-        const float qq = qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3];
-        for (int c = c0; c < nchunk; c += S::parts) {
-            float kv[8];
-            float al8[8];
-#pragma unroll
-            for (int e2 = 0; e2 < 4; ++e2) {
-                const v4f ca = kScalar ? czg[4 * c + e2] : cza[4 * c + e2];
-                al8[2 * e2] = ca.y;
-                al8[2 * e2 + 1] = ca.w;
-                const float cz[2] = {ca.x, ca.z};
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int e = 2 * e2 + h;
-                    const v4f z2 = kScalar ? zsg[8 * c + e] : zs[8 * c + e];
-                    float acc = cz[h] - qq;
-                    acc = fmaf(qs[0], z2.x, acc);
-                    acc = fmaf(qs[1], z2.y, acc);
-                    acc = fmaf(qs[2], z2.z, acc);
-                    acc = fmaf(qs[3], z2.w, acc);
-                    kv[e] = __builtin_amdgcn_exp2f(acc);
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) msum = fmaf(kv[e], al8[e], msum);
-            uint4 hv;
-            hv.x = pack_bf16x2(kv[0], kv[1]);
-            hv.y = pack_bf16x2(kv[2], kv[3]);
-            hv.z = pack_bf16x2(kv[4], kv[5]);
-            hv.w = pack_bf16x2(kv[6], kv[7]);
-            const int idx = (c >> 1) * 64 + s32 + 32 * (c & 1);
-            reinterpret_cast<uint4 *>(kg)[idx] = hv;
-            if constexpr (PREC == GPMPPI_BF16X3) {
-                uint4 lv;
-                lv.x = pack_bf16x2(kv[0] - bf16_to_f32((uint16_t)hv.x), kv[1] - bf16_to_f32((uint16_t)(hv.x >> 16)));
-                lv.y = pack_bf16x2(kv[2] - bf16_to_f32((uint16_t)hv.y), kv[3] - bf16_to_f32((uint16_t)(hv.y >> 16)));
-                lv.z = pack_bf16x2(kv[4] - bf16_to_f32((uint16_t)hv.z), kv[5] - bf16_to_f32((uint16_t)(hv.z >> 16)));
-                lv.w = pack_bf16x2(kv[6] - bf16_to_f32((uint16_t)hv.w), kv[7] - bf16_to_f32((uint16_t)(hv.w >> 16)));
-                reinterpret_cast<uint4 *>(kg + (size_t)Mpad * 64)[idx] = lv;
-            }
-        }
     }
     // per-part partial means: the lanes of a part hold distinct samples
     if constexpr (!mfma_gen<PREC>()) pred[part * S::B + sl] = msum;

@@ -15,14 +15,10 @@ namespace gpmppi {
 //  alpha  [2][Mpad]     (K + sn^2 I)^-1 y, zero beyond M
 //  w32    packed FP32 blocks of W = L^-1 (see pack layout in gp_build.hip)
 //  wbh/wbl packed BF16 hi / lo splits of the same blocks
-//  zs2    [2][Mpad][4]  2 zs, and cza [2][Mpad][2] (c2_o - |zs_oj|^2, alpha_oj):
-//                       the expanded exponent c2 - |q|^2 - |zs|^2 + 2 q.zs used by
-//                       the BF16 forms
+//  zop    BF16 A operands of the kernel-vector exponent products (BF16 forms)
 struct GpDev {
     const float *zs;
     const float *alpha;
-    const float *zs2;
-    const float *cza;
     const float4 *w32;
     const uint4 *wbh;
     const uint4 *wbl;

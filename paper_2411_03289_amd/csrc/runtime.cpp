@@ -407,8 +407,6 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
 
     c->gp.zs = c->zs;
     c->gp.alpha = c->alpha;
-    c->gp.zs2 = c->zs2;
-    c->gp.cza = c->cza;
     c->gp.w32 = c->w32;
     c->gp.wbh = c->wbh;
     c->gp.wbl = c->wbl;
