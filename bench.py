@@ -14,9 +14,10 @@ workgroup); the choice is reported per form.
 
 Forms: fp32 (FP32 matrix cores), bf16x3 (hi+lo BF16 splits), bf16 (plain
 BF16) for the variance contraction k^T (K + sn^2 I)^-1 k.  Each form is timed
-for --warmup + --steps iterations; the reported `value` is that of the fastest
-form whose new controls stay within 1e-3 of the FP64 oracle (stored oracle
-output tests/golden/c2_oracle.npz).
+for --warmup + --steps iterations (mean per iteration, and the median, 10th and
+90th percentiles of the single iterations); the reported `value` is that of the
+fastest form whose new controls stay within 1e-3 of the FP64 oracle (stored
+oracle output tests/golden/c2_oracle.npz).
 
 Prints ONE JSON line on stdout.
 """
@@ -271,8 +272,13 @@ def main():
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1) / args.steps
         rollout_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(r0, r1)]))
+        # per-iteration times (rollout + weights/update): from one iteration's start to the next's
+        starts = r0 + [e1]
+        it_ms = np.array([starts[i].elapsed_time(starts[i + 1]) for i in range(args.steps)])
         u_err = float(np.max(np.abs(U_out.cpu().numpy().astype(np.float64) - U_ref))) if U_ref is not None else None
         results[name] = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall / args.steps,
+                             iteration_ms={"median": float(np.median(it_ms)), "p10": float(np.percentile(it_ms, 10)),
+                                           "p90": float(np.percentile(it_ms, 90))},
                              sample_steps_per_s=K * T / (ms * 1e-3), rollout_kernel_ms=rollout_ms,
                              u_err_vs_fp64=u_err,
                              shape={k: shape[k] for k in ("groups", "rotate", "waves")})
