@@ -191,20 +191,19 @@ hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_
 }
 
 __global__ void combine_alpha_kernel(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w,
-                                     double *out64, float *alpha32, float *cza) {
+                                     double *out64, float *alpha32) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Mpad) return;
     double a = 0.0;
     for (int i = 0; i < n_terr; ++i) a += w.w[i] * alpha_terr[(size_t)i * Mpad + j];
     if (out64) out64[j] = a;
     alpha32[j] = (float)a;
-    cza[2 * j + 1] = (float)a;
 }
 
 hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w, double *out64,
-                         float *alpha32, float *cza, hipStream_t st) {
+                         float *alpha32, hipStream_t st) {
     hipLaunchKernelGGL(combine_alpha_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, alpha_terr, n_terr, Mpad, w,
-                       out64, alpha32, cza);
+                       out64, alpha32);
     return hipGetLastError();
 }
 
@@ -335,7 +334,7 @@ __global__ void pack_w_kernel(const double *W, int M, int Mpad, float4 *w32, uin
 }
 
 __global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int Mpad, double s0, double s1,
-                                double s2, double s3, double c2, float *zs, float *al, float *zs2, float *cza) {
+                                double s2, double s3, double c2, float *zs, float *al, float *zs2, float *cz) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= Mpad) return;
     double z[4] = {0.0, 0.0, 0.0, 0.0}, a = 0.0;
@@ -354,8 +353,7 @@ __global__ void pack_vec_kernel(const double *Z, const double *alpha, int M, int
         zz += (double)zf[d] * (double)zf[d];
     }
     al[j] = (float)a;
-    cza[2 * j] = (float)(c2 - zz);
-    cza[2 * j + 1] = (float)a;
+    cz[j] = (float)(c2 - zz);
 }
 
 // Three BF16 terms whose sum is the FP32 value x (round to nearest even at
@@ -385,7 +383,7 @@ __device__ __forceinline__ void split3_bf16(float x, uint16_t &h, uint16_t &m, u
 // up with points 8 (l / 32) + r (r < 8) and 16 + 8 (l / 32) + r - 8: the k operand
 // of the variance products in its lane order without any exchange.
 // zop[(jt * 2 + step) * 64 + lane] = 8 BF16 slots 8 (lane / 32) .. + 7 of row lane % 32.
-__global__ void pack_zop_kernel(const float *zs2, const float *cza, int Mpad, uint4 *zop) {
+__global__ void pack_zop_kernel(const float *zs2, const float *cz, int Mpad, uint4 *zop) {
     const int NT = Mpad / 32;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NT * 128) return;
@@ -395,7 +393,7 @@ __global__ void pack_zop_kernel(const float *zs2, const float *cza, int Mpad, ui
     const int j = 32 * jt + 16 * (a >> 1) + 8 * bb + 4 * (a & 1) + c;
     uint16_t zh[4], zm[4], zl[4], ch, cm, cl;
     for (int d = 0; d < 4; ++d) split3_bf16(zs2[4 * j + d], zh[d], zm[d], zl[d]);
-    split3_bf16(cza[2 * j], ch, cm, cl);
+    split3_bf16(cz[j], ch, cm, cl);
     const uint16_t one = 0x3f80;
     uint16_t slot[16];
     if (step == 0) {
@@ -429,13 +427,13 @@ __global__ void pack_zop_kernel(const float *zs2, const float *cza, int Mpad, ui
 }
 
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, uint4 *zop,
-                          float *zs, float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
+                          float *zs, float *alpha, float *zs2, float *cz, float4 *w32, uint4 *wbh, uint4 *wbl,
                           hipStream_t st) {
     const int NP = (Mpad / 32 + 1) / 2;
     hipLaunchKernelGGL(pack_w_kernel, dim3(2 * NP * (NP + 1)), dim3(64), 0, st, b.W, M, Mpad, w32, wbh, wbl);
     hipLaunchKernelGGL(pack_vec_kernel, dim3((Mpad + 255) / 256), dim3(256), 0, st, b.Z, b.alpha, M, Mpad,
-                       scale[0], scale[1], scale[2], scale[3], c2, zs, alpha, zs2, cza);
-    hipLaunchKernelGGL(pack_zop_kernel, dim3((Mpad / 32 * 128 + 255) / 256), dim3(256), 0, st, zs2, cza, Mpad, zop);
+                       scale[0], scale[1], scale[2], scale[3], c2, zs, alpha, zs2, cz);
+    hipLaunchKernelGGL(pack_zop_kernel, dim3((Mpad / 32 * 128 + 255) / 256), dim3(256), 0, st, zs2, cz, Mpad, zop);
     return hipGetLastError();
 }
 

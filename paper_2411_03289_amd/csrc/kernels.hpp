@@ -138,9 +138,9 @@ struct TerrainWeights {
     double w[8];
 };
 // alpha_bar = sum_i w_i alpha_i (FP64 alpha_terr [n_terr][Mpad] of one output),
-// written to out64 and, in FP32, to alpha32 [Mpad] and the alpha slots of cza.
+// written to out64 and, in FP32, to alpha32 [Mpad].
 hipError_t combine_alpha(const double *alpha_terr, int n_terr, int Mpad, TerrainWeights w, double *out64,
-                         float *alpha32, float *cza, hipStream_t st);
+                         float *alpha32, hipStream_t st);
 hipError_t launch_terrain_means(const float *q, int n, const GpDev &g, const double *alpha_terr, int n_terr,
                                 float *out, hipStream_t st);
 // Differentiation form (the adjoint rollout and its reductions).
@@ -181,7 +181,7 @@ hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st);
 hipError_t pack_q(const GpBuildBuffers &b, int M, int Mpad, float4 *q32, hipStream_t st);
 hipError_t alpha_for_targets(const GpBuildBuffers &b, int Mpad, const double *y_d, double *alpha_d, hipStream_t st);
 hipError_t pack_gp_output(const GpBuildBuffers &b, int M, int Mpad, const double scale[4], double c2, uint4 *zop, float *zs,
-                          float *alpha, float *zs2, float *cza, float4 *w32, uint4 *wbh, uint4 *wbl,
+                          float *alpha, float *zs2, float *cz, float4 *w32, uint4 *wbh, uint4 *wbl,
                           hipStream_t st);
 
 }  // namespace gpmppi

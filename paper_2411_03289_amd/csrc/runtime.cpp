@@ -82,7 +82,7 @@ struct gpmppi_ctx {
     int M = 0, Mpad = 0, NT = 0;
     double z_p = 0, c_p = 0;
     // device buffers
-    float *zs = nullptr, *alpha = nullptr, *zs2 = nullptr, *cza = nullptr;
+    float *zs = nullptr, *alpha = nullptr, *zs2 = nullptr, *cz = nullptr;
     int groups = 1;                  // sample groups of 32 per rollout workgroup (tuned)
     int waves = 4;                   // wave64s per rollout workgroup, 4 or 8 (tuned)
     int rotate = 1;                  // block-dependent start of the walk over W (tuned)
@@ -232,7 +232,7 @@ gpmppi_status build_gps(gpmppi_ctx *c, const gpmppi_gp gp[2]) {
         const double c2 = 2.0 * gp[o].log_sf / std::log(2.0);
         HIP_TRY(pack_gp_output(b, M, Mpad, scale, c2, c->zop + o * c->zop_stride, c->zs + (size_t)o * Mpad * 4,
                                c->alpha + (size_t)o * Mpad,
-                               c->zs2 + (size_t)o * Mpad * 4, c->cza + (size_t)o * Mpad * 2,
+                               c->zs2 + (size_t)o * Mpad * 4, c->cz + (size_t)o * Mpad,
                                c->w32 + o * c->w32_stride, c->wbh + o * c->wb_stride, c->wbl + o * c->wb_stride,
                                nullptr));
         if (c->q32) HIP_TRY(pack_q(b, M, Mpad, c->q32 + (size_t)o * c->q_stride, nullptr));
@@ -350,7 +350,7 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->zs = track(dev_alloc<float>((size_t)2 * Mpad * 4, st));
     c->alpha = track(dev_alloc<float>((size_t)2 * Mpad, st));
     c->zs2 = track(dev_alloc<float>((size_t)2 * Mpad * 4, st));
-    c->cza = track(dev_alloc<float>((size_t)2 * Mpad * 2, st));
+    c->cz = track(dev_alloc<float>((size_t)2 * Mpad, st));
     c->w32 = track(dev_alloc<float4>((size_t)2 * c->w32_stride, st));
     c->wbh = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
     c->wbl = track(dev_alloc<uint4>((size_t)2 * c->wb_stride, st));
@@ -517,7 +517,7 @@ gpmppi_status gpmppi_set_terrain_weights(gpmppi_ctx *c, const double *w) {
     const int Mpad = c->Mpad;
     for (int o = 0; o < 2; ++o) {
         HIP_TRY(combine_alpha(c->alpha_terr + (size_t)o * c->n_terr * Mpad, c->n_terr, Mpad, tw, nullptr,
-                              c->alpha + (size_t)o * Mpad, c->cza + (size_t)o * Mpad * 2, nullptr));
+                              c->alpha + (size_t)o * Mpad, nullptr));
         c->gp.vscale[o] = (float)s2;
     }
     HIP_TRY(hipDeviceSynchronize());
