@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sample-steps/s + MPPI iter ms (K=16384,T=100,M=1024), BF16 vs FP32 at stated err"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+HBM_PEAK_BPS = 8e12
 FORMS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 U_ERR_BAR = 1e-3
 
@@ -291,6 +292,7 @@ def main():
     r = results[best]
     achieved = flops_per_launch / (r["rollout_kernel_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[best]
+    traffic = measured_traffic(best)
     line = {
         "metric": METRIC,
         "value": r["sample_steps_per_s"],
@@ -307,7 +309,8 @@ def main():
         "config": {"workload": "GP-MPPI iteration K=16384 T=100 M=1024 (2 outputs, d=4), 50 obstacles, "
                                "figure-eight P=256", "form": best, "K": K, "T": T, "M": M},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(best), "traffic_unit": "bytes per launch",
+                     "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "hbm_frac": (traffic / (r["rollout_kernel_ms"] * 1e-3) / HBM_PEAK_BPS) if traffic else None,
                      "kernel": "rollout_kernel", "flops_per_launch": flops_per_launch},
         "forms": results,
         "speedup_vs_fp32": {n: results["fp32"]["ms_per_step"] / results[n]["ms_per_step"]
