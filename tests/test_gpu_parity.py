@@ -417,7 +417,8 @@ def test_terrain_means_feed_the_weight_estimate():
 
 def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
     t = torch()
-    # M = 300: 10 row tiles in 5 row-tile pairs, so that the walk's start rotation matters
+    # M = 300: 10 row tiles, walked as single row tiles (5 pairs cannot be spread evenly over 4 or 8
+    # waves), several per wave, so that the walk's start rotation matters
     pr = W.make_config(0, K=300, T=12, M=300, N=300)
     S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
     ctx = B.gpmppi_init(pr, B.FP32)
