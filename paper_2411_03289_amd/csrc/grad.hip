@@ -9,11 +9,12 @@
 //
 // grad_kernel: one workgroup of 256 threads per 32 samples (one 32-column
 // matrix-core group; 8 loop parts = 4 waves x 2 half-waves).
-//   job 0   forward over all T steps: costs, and the state (x, Sigma) every C
-//           steps (checkpoints);
+//   job 0   forward over all T steps: costs, the state (x, Sigma) every C
+//           steps (checkpoints), and the last segment's per-step record;
 //   job j   for segment n - j (last first): recompute the segment's C steps
-//           from its checkpoint, keeping per-step state, controls, GP means
-//           and variances in a scratch array, then step backwards through it.
+//           from its checkpoint (not for j = 1, recorded by job 0), keeping
+//           per-step state, controls, GP means and variances in a scratch
+//           array, then step backwards through it.
 // Both passes run the same forward code, so the recomputed trajectory is the
 // first pass's bit for bit.  Per backward step, per sample, in registers: the
 // adjoints of the stage cost, of Sigma+ = A Sigma A^T + dt^2 diag(s2) (the
@@ -232,11 +233,15 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     float pb[15] = {};
     float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
 
+    // the last segment's per-step record is written by the forward pass itself, so
+    // its backward job (job 1) needs no recompute
+    const int kl0 = (nseg - 1) * C;
     for (int job = 0; job <= nseg; ++job) {
         const bool first = job == 0;
         const int segi = first ? 0 : nseg - job;
         const int k0 = first ? 0 : segi * C;
         const int k1 = first ? T : min(T, k0 + C);
+        const int kf = job == 1 ? k0 : k1;   // end of the forward (re)computation: job 1's is recorded
         if (first) {
             X = a.x0[0]; Y = a.x0[1]; th = a.x0[2]; v = a.x0[3]; w_ = a.x0[4];
 #pragma unroll
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
         }
         restage(g, (k0 & 1) ? 1 : 0, lds);
         // ---------------------------------------------------------- forward
-        for (int k = k0; k < k1; ++k) {
+        for (int k = k0; k < kf; ++k) {
             if (writer) {
                 if (first && k % C == 0 && valid) {
                     float *ck = a.ckpt + (size_t)(k / C) * kCkF * K + sg;
@@ -259,8 +264,8 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 #pragma unroll
                     for (int i = 0; i < 15; ++i) ck[(5 + i) * (size_t)K] = p[i];
                 }
-                if (!first) {
-                    float *e = segw + (size_t)(k - k0) * kSegF * kB;
+                if (!first || k >= kl0) {
+                    float *e = segw + (size_t)(k - (first ? kl0 : k0)) * kSegF * kB;
                     seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
 #pragma unroll
                     for (int i = 0; i < 15; ++i) seg_put(e, 5 + i, p[i]);
@@ -292,8 +297,8 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 #pragma unroll
             for (int i = 0; i < 15; ++i) p[i] = P[i];
             X = Xn; Y = Yn; th = thn; v = vn; w_ = wn;
-            if (!first && writer) {
-                float *e = segw + (size_t)(k - k0) * kSegF * kB;
+            if ((!first || k >= kl0) && writer) {
+                float *e = segw + (size_t)(k - (first ? kl0 : k0)) * kSegF * kB;
                 seg_put(e, 20, u.x); seg_put(e, 21, u.y); seg_put(e, 22, m[0]); seg_put(e, 23, m[1]);
                 seg_put(e, 24, s2[0]); seg_put(e, 25, s2[1]);
                 seg_put(e, 26, s2[0] > g.sn2[0] ? 1.0f : 0.0f);
@@ -318,9 +323,15 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
         }
         if (first) {
             if (writer && valid) a.costs[sg] = S_;
+            if (writer) {   // the last segment's final state
+                float *e = segw + (size_t)(T - kl0) * kSegF * kB;
+                seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
+#pragma unroll
+                for (int i = 0; i < 15; ++i) seg_put(e, 5 + i, p[i]);
+            }
             continue;
         }
-        if (writer) {   // the segment's final state
+        if (job != 1 && writer) {   // the segment's final state
             float *e = segw + (size_t)(k1 - k0) * kSegF * kB;
             seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
 #pragma unroll
