@@ -135,11 +135,17 @@ __device__ __forceinline__ void constraint_scan(const Geometry &geo, float X, fl
                                                 float &best_all, int &iseg, float &om_all, int &iobs) {
     float best = INFINITY, om = INFINITY;
     int bi = -1, oi = -1;
+    // wave-uniform indices (both half-waves take the same segments and obstacles and
+    // store the same results): the geometry comes through the scalar cache
+    const int wu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (geo.path_kind != 0) {
-        for (int i = part; i < geo.P; i += kParts) {
-            const float4 sgm = geo.seg[i];
+        const const_v4p segs = (const_v4p)geo.seg;
+        const const_fp sinv = (const_fp)geo.seg_inv;
+#pragma unroll 4
+        for (int i = wu; i < geo.P; i += kWaves) {
+            const v4f sgm = segs[i];
             const float rx = X - sgm.x, ry = Y - sgm.y;
-            float t = (rx * sgm.z + ry * sgm.w) * geo.seg_inv[i];
+            float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
             t = fminf(fmaxf(t, 0.0f), 1.0f);
             const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
             const float d2 = ex * ex + ey * ey;
@@ -149,8 +155,10 @@ __device__ __forceinline__ void constraint_scan(const Geometry &geo, float X, fl
             }
         }
     }
-    for (int j = part; j < geo.n_obs; j += kParts) {
-        const float4 ob = geo.obs[j];
+    const const_v4p obs = (const_v4p)geo.obs;
+#pragma unroll 2
+    for (int j = wu; j < geo.n_obs; j += kWaves) {
+        const v4f ob = obs[j];
         const float dx = X - ob.x, dyy = Y - ob.y;
         const float rho2 = dx * dx + dyy * dyy;
         const float rho = sqrtf(rho2);
