@@ -415,6 +415,34 @@ def test_terrain_means_feed_the_weight_estimate():
                                atol=1e-6)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_instances_at_every_shape_match_oracle(seed):
+    # fixed-seed instances of uneven K, T, M, obstacle count, track and nominal controls, at every
+    # admissible launch shape: both walks over W (row-tile pairs, single row tiles) across many
+    # row-tile counts, ragged sample blocks, and the geometry loops inside the contraction
+    rng = np.random.Generator(np.random.PCG64(9000 + seed))
+    K, T, M = int(rng.integers(1, 400)), int(rng.integers(1, 14)), int(rng.integers(1, 700))
+    n_obs, path = int(rng.integers(0, 9)), ("eight" if rng.integers(0, 2) else "circle")
+    pr = W.small_problem(K=K, T=T, M=M, n_obs=n_obs, path=path, seed_data=100 + seed,
+                         U_scale=float(rng.uniform(0.0, 1.5)), n_data=max(M, 50))
+    print(f"instance {seed}: K={K} T={T} M={M} n_obs={n_obs} path={path}", flush=True)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    n_shapes = 0
+    for groups in (1, 2):
+        for rotate in (0, 1):
+            for waves in (4, 8):
+                try:
+                    B.gpmppi_set_tuning(ctx, groups, rotate, waves)
+                except B.GpmppiError:
+                    assert groups == 2   # two sample groups need both k operands in LDS
+                    continue
+                S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+                _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"instance {seed} groups={groups} rotate={rotate} waves={waves}")
+                n_shapes += 1
+    assert n_shapes >= 4
+
+
 def test_every_tuned_shape_matches_oracle_and_the_tuner_installs_its_choice():
     t = torch()
     # M = 300: 10 row tiles, walked as single row tiles (5 pairs cannot be spread evenly over 4 or 8
