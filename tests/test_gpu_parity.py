@@ -116,33 +116,72 @@ def test_gp_predict_bf16_forms_ragged(M):
             assert np.all(gv[o] >= g.sn2 * (1 - 1e-6))
 
 
-@pytest.mark.parametrize("prec", [B.BF16X3, B.BF16])
-def test_bf16_rollout_states_at_every_shape(prec):
-    """BF16-form rollouts at M = 300 (ten column tiles over four or eight waves) for every launch
-    shape: the state trajectory depends on the GP mean only, which stays FP32 in these forms, so
-    states, controls and means follow the oracle at the FP32 bar; the variance meets the form's."""
-    pr = W.small_problem(K=150, T=10, M=300, n_obs=7, path="eight", seed_data=26, U_scale=1.0)
-    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
-    vtol = 5e-5 if prec == B.BF16X3 else 2e-2
-    # FP32 dot-product bound of each step's GP mean: sum_j |k_j alpha_j| at the oracle's inputs
+def _bf16_bounds(pr, tr_o):
+    """FP32 dot-product bound of each step's GP mean: sum_j |k_j alpha_j| at the oracle's inputs."""
     q = np.concatenate([tr_o.x[:-1, :, 3:5], tr_o.u], axis=2).reshape(-1, 4)
     absdot = np.stack([np.abs(G.se_ard(q, g.Z, g.log_ell, g.log_sf)) @ np.abs(g.alpha)
                        for g in G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)], axis=1)
-    absdot = absdot.reshape(pr.T, pr.K, 2)
+    return absdot.reshape(pr.T, pr.K, 2)
+
+
+def _check_bf16_rollout(prec, S_g, tr_g, tr_o, absdot, label):
+    """The state trajectory depends on the GP mean only, which stays FP32 in the BF16 forms, so
+    states, controls and means follow the oracle at the FP32 bar; the variance meets the form's."""
+    vtol = 5e-5 if prec == B.BF16X3 else 2e-2
+    ex = rel_err(tr_g["x"], tr_o.x, 1.0)
+    em = np.abs(tr_g["gp_mean"] - tr_o.gp_mean)
+    ev = np.abs(tr_g["gp_var"] - tr_o.gp_var)
+    _print(label, x=ex.max(), gp_mean=em.max(), gp_var=ev.max())
+    assert np.all(ex <= TOL), "states"
+    assert np.all(np.abs(tr_g["u"] - tr_o.u) <= 1e-5), "sampled controls"
+    assert np.all(em <= 1e-5 + 8 * EPS32 * absdot), "gp mean"
+    assert ev.max() <= vtol, "gp variance"
+    assert np.all(np.isfinite(S_g))
+
+
+@pytest.mark.parametrize("prec", [B.BF16, B.BF16X3])
+def test_bf16_rollout_states_at_every_shape(prec):
+    """BF16-form rollouts at M = 300 (ten column tiles over four or eight waves) for every launch
+    shape."""
+    pr = W.small_problem(K=150, T=10, M=300, n_obs=7, path="eight", seed_data=26, U_scale=1.0)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    absdot = _bf16_bounds(pr, tr_o)
     ctx = B.gpmppi_init(pr, prec)
     for groups in (1, 2):
         for waves in (4, 8):
             B.gpmppi_set_tuning(ctx, groups, 1, waves)
             S_g, tr_g = gpu_rollout(pr, ctx=ctx)
-            ex = rel_err(tr_g["x"], tr_o.x, 1.0)
-            em = np.abs(tr_g["gp_mean"] - tr_o.gp_mean)
-            ev = np.abs(tr_g["gp_var"] - tr_o.gp_var)
-            _print(f"form={prec} groups={groups} waves={waves}", x=ex.max(), gp_mean=em.max(), gp_var=ev.max())
-            assert np.all(ex <= TOL), "states"
-            assert np.all(np.abs(tr_g["u"] - tr_o.u) <= 1e-5), "sampled controls"
-            assert np.all(em <= 1e-5 + 8 * EPS32 * absdot), "gp mean"
-            assert ev.max() <= vtol, "gp variance"
-            assert np.all(np.isfinite(S_g))
+            _check_bf16_rollout(prec, S_g, tr_g, tr_o, absdot, f"form={prec} groups={groups} waves={waves}")
+
+
+@pytest.mark.parametrize("prec", [B.BF16, B.BF16X3])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_instances_bf16_forms_at_every_shape(prec, seed):
+    # fixed-seed instances of uneven K, T, M (up to 1024: both walks, and two sample groups where
+    # the form's k operands fit), obstacle count and track
+    rng = np.random.Generator(np.random.PCG64(9700 + seed))
+    K, T, M = int(rng.integers(1, 300)), int(rng.integers(1, 12)), int(rng.integers(1, 1025))
+    n_obs, path = int(rng.integers(0, 9)), ("eight" if rng.integers(0, 2) else "circle")
+    pr = W.small_problem(K=K, T=T, M=M, n_obs=n_obs, path=path, seed_data=200 + seed,
+                         U_scale=float(rng.uniform(0.0, 1.5)), n_data=max(M, 50))
+    print(f"instance {seed}: K={K} T={T} M={M} n_obs={n_obs} path={path}", flush=True)
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
+    absdot = _bf16_bounds(pr, tr_o)
+    ctx = B.gpmppi_init(pr, prec)
+    n_shapes = 0
+    for groups in (1, 2):
+        for rotate in (0, 1):
+            for waves in (4, 8):
+                try:
+                    B.gpmppi_set_tuning(ctx, groups, rotate, waves)
+                except B.GpmppiError:
+                    assert groups == 2
+                    continue
+                S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+                _check_bf16_rollout(prec, S_g, tr_g, tr_o, absdot,
+                                    f"form={prec} instance {seed} groups={groups} rotate={rotate} waves={waves}")
+                n_shapes += 1
+    assert n_shapes >= 4
 
 
 def test_not_positive_definite_is_reported():
