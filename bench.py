@@ -112,8 +112,8 @@ def extras(B, W, torch, log_fn):
     """Informational timings of the other workloads (not the reported value):
     c1 closed loop (K=4096, T=50, M=256, 100 steps, HIP graph), c3 batch (64
     problems of uneven shape, 50 closed-loop steps in one persistent launch per
-    step, HIP graph, tuned), c4 gradient (K=4096, T=50, M=512, tau 0.05 m,
-    checkpoints every 10 steps)."""
+    step, HIP graph, tuned; FP32, and the same in the BF16 form), c4 gradient
+    (K=4096, T=50, M=512, tau 0.05 m, checkpoints every 10 steps)."""
     import numpy as np
     out = {}
     f32 = dict(device="cuda", dtype=torch.float32)
@@ -165,6 +165,29 @@ def extras(B, W, torch, log_fn):
         del b
     except Exception as exc:
         out["c3_batch"] = {"error": repr(exc)}
+    try:   # c3 batch in the BF16 form (informational: the batching and precision forms together)
+        probs = [W.make_batch_problem(p) for p in range(64)]
+        b = B.gpmppi_batch_init(probs, B.BF16)
+        x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), **f32)
+        U0 = torch.tensor(np.concatenate([p.U0.reshape(-1) for p in probs]), **f32)
+        shape = B.gpmppi_batch_tune(b, x0, U0, probs[0].seed, 1, stream)
+        x, U = x0.clone(), U0.clone()
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 2, 0.3, use_graph=True, stream=stream)   # warm-up
+        x, U = x0.clone(), U0.clone()
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 50, 0.3, use_graph=True, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        ss = sum(p.K * p.T for p in probs)
+        out["c3_batch_bf16"] = {"ms_per_control_step": ms, "sample_steps_per_s": ss / (ms * 1e-3), "shape": shape,
+                                "workload": "the c3 batch in the BF16 form (informational)"}
+        log_fn(f"[bench] extra c3 batch bf16 {ms:.3f} ms/step")
+        del b
+    except Exception as exc:
+        out["c3_batch_bf16"] = {"error": repr(exc)}
     try:   # c4 gradient
         pr = W.make_config(4)
         ctx = B.gpmppi_init(pr, B.FP32)
