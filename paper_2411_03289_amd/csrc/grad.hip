@@ -89,7 +89,11 @@ __device__ __forceinline__ void gen_kvec(const GpDev &g, int o, const float qs[4
 }
 
 // r = Q k for the block's 32 samples: wave w computes row tiles t = w, w+4, ...
-// over all column tiles, writing r[s][j] (row stride Mpad + 1) to LDS.
+// over all column tiles, writing r[s][j] (row stride Mpad + 1) to LDS.  Q blocks
+// rotate through three register slots: block it + 2 is loaded into the slot of
+// block it - 1, whose products have read their operands by then, so a load never
+// waits on the products of the block it replaces (loads past the row's end
+// repeat its last block).
 __device__ __forceinline__ void qk_walk(const GradArgs &a, int o, unsigned char *lds) {
     const int Mpad = a.gp.Mpad, NT = Mpad >> 5;
     const int lane = threadIdx.x & 63;
@@ -97,27 +101,36 @@ __device__ __forceinline__ void qk_walk(const GradArgs &a, int o, unsigned char 
     const float4 *Qo = a.q32 + (size_t)o * a.q_stride;
     float *rb = reinterpret_cast<float *>(lds + grad_rbuf_off(Mpad));
     for (int t = w; t < NT; t += kWaves) {
+        const float4 *Qt = Qo + (size_t)(t * NT) * 256 + lane;
         v16f acc = v16f{};
-        WBlock<GPMPPI_FP32> cur, nxt;
-        {
-            const float4 *p = Qo + (size_t)(t * NT) * 256 + lane;
-            cur.v[0] = p[0];
-            cur.v[1] = p[64];
-            cur.v[2] = p[128];
-            cur.v[3] = p[192];
+        WBlock<GPMPPI_FP32> b[3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const float4 *p = Qt + (size_t)(r < NT ? r : NT - 1) * 256;
+            b[r].v[0] = p[0];
+            b[r].v[1] = p[64];
+            b[r].v[2] = p[128];
+            b[r].v[3] = p[192];
         }
-        for (int it = 0; it < NT; ++it) {
-            if (it + 1 < NT) {
-                const float4 *p = Qo + (size_t)(t * NT + it + 1) * 256 + lane;
-                nxt.v[0] = p[0];
-                nxt.v[1] = p[64];
-                nxt.v[2] = p[128];
-                nxt.v[3] = p[192];
+        for (int it0 = 0; it0 < NT; it0 += 3) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int it = it0 + r;
+                if (it < NT) {
+                    {   // block it + 2 into the slot freed by block it - 1
+                        const int nx = it + 2 < NT ? it + 2 : NT - 1;
+                        const float4 *p = Qt + (size_t)nx * 256;
+                        WBlock<GPMPPI_FP32> &d = b[(r + 2) % 3];
+                        d.v[0] = p[0];
+                        d.v[1] = p[64];
+                        d.v[2] = p[128];
+                        d.v[3] = p[192];
+                    }
+                    KOp<GPMPPI_FP32> kop;
+                    load_kop<GPMPPI_FP32>(kop, lds, it, lane, Mpad);
+                    mma_block<GPMPPI_FP32>(acc, b[r], kop);
+                }
             }
-            KOp<GPMPPI_FP32> kop;
-            load_kop<GPMPPI_FP32>(kop, lds, it, lane, Mpad);
-            mma_block<GPMPPI_FP32>(acc, cur, kop);
-            cur = nxt;
         }
         const int s = lane & 31;
 #pragma unroll
