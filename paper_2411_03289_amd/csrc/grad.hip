@@ -90,10 +90,9 @@ __device__ __forceinline__ void gen_kvec(const GpDev &g, int o, const float qs[4
 
 // r = Q k for the block's 32 samples: wave w computes row tiles t = w, w+4, ...
 // over all column tiles, writing r[s][j] (row stride Mpad + 1) to LDS.  Q blocks
-// rotate through three register slots: block it + 2 is loaded into the slot of
-// block it - 1, whose products have read their operands by then, so a load never
-// waits on the products of the block it replaces (loads past the row's end
-// repeat its last block).
+// rotate through four register slots with static indices: block it + 3 is loaded
+// into the slot of block it - 1 before the products of block it (loads past the
+// row's end repeat its last block), three blocks of products ahead of its use.
 __device__ __forceinline__ void qk_walk(const GradArgs &a, int o, unsigned char *lds) {
     const int Mpad = a.gp.Mpad, NT = Mpad >> 5;
     const int lane = threadIdx.x & 63;
@@ -103,24 +102,24 @@ __device__ __forceinline__ void qk_walk(const GradArgs &a, int o, unsigned char 
     for (int t = w; t < NT; t += kWaves) {
         const float4 *Qt = Qo + (size_t)(t * NT) * 256 + lane;
         v16f acc = v16f{};
-        WBlock<GPMPPI_FP32> b[3];
+        WBlock<GPMPPI_FP32> b[4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < 3; ++r) {
             const float4 *p = Qt + (size_t)(r < NT ? r : NT - 1) * 256;
             b[r].v[0] = p[0];
             b[r].v[1] = p[64];
             b[r].v[2] = p[128];
             b[r].v[3] = p[192];
         }
-        for (int it0 = 0; it0 < NT; it0 += 3) {
+        for (int it0 = 0; it0 < NT; it0 += 4) {
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
+            for (int r = 0; r < 4; ++r) {
                 const int it = it0 + r;
                 if (it < NT) {
-                    {   // block it + 2 into the slot freed by block it - 1
-                        const int nx = it + 2 < NT ? it + 2 : NT - 1;
+                    {   // block it + 3 into the slot freed by block it - 1
+                        const int nx = it + 3 < NT ? it + 3 : NT - 1;
                         const float4 *p = Qt + (size_t)nx * 256;
-                        WBlock<GPMPPI_FP32> &d = b[(r + 2) % 3];
+                        WBlock<GPMPPI_FP32> &d = b[(r + 3) % 4];
                         d.v[0] = p[0];
                         d.v[1] = p[64];
                         d.v[2] = p[128];
