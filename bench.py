@@ -122,7 +122,7 @@ def extras(B, W, torch, log_fn):
     try:   # c1 closed loop
         pr = W.make_config(1)
         ctx = B.gpmppi_init(pr, B.FP32)
-        B.gpmppi_tune(ctx, torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32), pr.seed, 2, stream)
+        shape = B.gpmppi_tune(ctx, torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32), pr.seed, 2, stream)
         x, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
         B.gpmppi_closed_loop(ctx, x, U, pr.seed, 5, 0.3, use_graph=True, stream=stream)   # warm-up
         x, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
@@ -134,7 +134,8 @@ def extras(B, W, torch, log_fn):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 100
         out["c1_closed_loop"] = {"ms_per_control_step": ms, "sample_steps_per_s": pr.K * pr.T / (ms * 1e-3),
-                                 "workload": "K=4096 T=50 M=256 20 obstacles figure-eight, 100 steps, HIP graph"}
+                                 "workload": "K=4096 T=50 M=256 20 obstacles figure-eight, 100 steps, HIP graph",
+                                 "shape": {k: shape[k] for k in ("groups", "rotate", "waves", "split")}}
         log_fn(f"[bench] extra c1 closed loop {ms:.3f} ms/step")
         del ctx
     except Exception as exc:   # informational only

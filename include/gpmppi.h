@@ -239,18 +239,22 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, 
  * None of these changes what is computed; they change the grouping of the
  * variance contraction's partial sums, so results differ between shapes only
  * by FP32 rounding.  Defaults: the largest group count that fits LDS,
- * rotate = 1, 4 waves, one workgroup per compute unit per 80 KB of LDS (at
- * most 2), longest items first. */
+ * rotate = 1, 4 waves, no output split, one workgroup per compute unit per
+ * 80 KB of LDS (at most 2), longest items first. */
 typedef struct {
     int32_t groups;      /* sample groups of 32 lanes per workgroup: 1 or 2 (2 only where the k operand fits LDS) */
     int32_t rotate;      /* 1: each workgroup starts its walk over W at a block-dependent row-pair; 0: at pair 0 */
     int32_t wg_per_cu;   /* batches: persistent workgroups per compute unit, 1 or 2 (LDS permitting) */
     int32_t order;       /* batches: 0 = items longest first, 1 = problem order */
     int32_t waves;       /* wave64s per rollout workgroup: 4 or 8 */
+    int32_t split;       /* contexts: 1 runs the two GP outputs of each 32-sample block on two workgroups
+                          * that exchange means and variances every step (groups = 1, and only where the
+                          * doubled grid fits the device at once; results equal those of split = 0);
+                          * batches: 0 */
     double ms;           /* tune: mean rollout time of this shape in ms; ignored by set */
 } gpmppi_tuning;
 
-/* Autotuner: times every admissible shape (groups x rotate x waves) with HIP events on `stream`
+/* Autotuner: times every admissible shape (groups x rotate x waves x split) with HIP events on `stream`
  * (1 warm-up + reps rollouts each, reps in [1, 100], into internal scratch
  * costs; x0_d [5] and U_d [T][2] as for gpmppi_rollout), installs the fastest
  * and writes it, with its time, to *chosen (may be NULL).  Synchronises. */

@@ -367,8 +367,11 @@ __device__ __forceinline__ void stage_store(const StagedInputs &st, const GpDev 
 }
 
 // BF16 bit patterns of three terms summing to the FP32 value x (round to
-// nearest even at each stage; the remainders are exact in FP32).
+// nearest even at each stage; the remainders are exact in FP32).  Contraction
+// is off: where x is a product, x - hi must not become a fused multiply-add of
+// the unrounded product, or the split would depend on the code around it.
 __device__ __forceinline__ void split3_bits(float x, uint32_t &h, uint32_t &m, uint32_t &l) {
+#pragma clang fp contract(off)
     const __bf16 bh = (__bf16)x;
     const float r1 = x - (float)bh;
     const __bf16 bm = (__bf16)r1;
@@ -537,7 +540,8 @@ __device__ __forceinline__ void gen_bop(const float qs[4], int hl, uint4 bop[G][
             const float other = (G == 2) ? shfl_xor(qs[d], 32) : qs[d];
             qv[d] = (G == 1 || hl == gg) ? qs[d] : other;
         }
-        const float qq = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
+        // explicit fused multiply-adds: the same rounding wherever this is inlined
+        const float qq = fmaf(qv[3], qv[3], fmaf(qv[2], qv[2], fmaf(qv[1], qv[1], qv[0] * qv[0])));
         uint32_t qh[4], qm[4], ql[4], nqq[3];
 #pragma unroll
         for (int d = 0; d < 4; ++d) split3_bits(qv[d], qh[d], qm[d], ql[d]);

@@ -72,6 +72,11 @@ struct RolloutArgs {
     float *costs;                   // [K]
     const float *tight_sxy;         // [T+1][3] Sigma_XY along the nominal sequence, or NULL (per sample)
     gpmppi_trace trace;
+    // output split (two workgroups per sample block): exchange records
+    // [nblk][4 slots][3 kinds][32 samples] of (value, tag) and the launch epoch
+    // and finished-workgroup count [2]; see rollout_block_split
+    unsigned long long *xrec;
+    uint32_t *xep;
 };
 
 struct UpdateArgs {
@@ -91,7 +96,12 @@ size_t rollout_lds_bytes(int precision, int G, int Mpad);
 // largest sample-group count whose LDS plan fits a compute unit (1 or 2)
 int rollout_groups(int precision, int Mpad);
 // G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8).
-hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, hipStream_t st);
+// split = 1: each sample block's two GP outputs on two workgroups (G = 1 only; a.xrec, a.xep set),
+// hipErrorCooperativeLaunchTooLarge if the doubled grid cannot be resident at once.
+hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st);
+// Largest sample count whose split launch at this shape can be resident at once (0: not admissible).
+int rollout_split_capacity(int precision, int Mpad, int NW);
+constexpr int kXchRecPerBlock = 4 * 3 * 32;   // exchange records per sample block
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
                                 int precision, int G, int NW, int Mpad_max, int grid, hipStream_t st);
 hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st);

@@ -45,6 +45,205 @@ __device__ __forceinline__ float obstacle_margin(float dx, float dy, float radiu
     return (rho - radius) - z_p * __builtin_amdgcn_sqrtf(fmaxf(vn, 0.0f));
 }
 
+// The 15 entries of a sample's symmetric 5x5 state covariance (Eq. 10).
+struct Cov {
+    float p00, p01, p02, p03, p04, p11, p12, p13, p14, p22, p23, p24, p33, p34, p44;
+};
+
+// Jacobian of the Euler step: identity plus a02, a03 (row x), a12, a13 (row y),
+// a24 (row theta), diagonal a33, a44 for the velocities.
+struct StepJac {
+    float a02, a03, a12, a13, a24, a33, a44;
+};
+
+__device__ __forceinline__ StepJac step_jacobian(const Dyn &dy, float v, float sth, float cth) {
+    const float dt = dy.dt;
+    return StepJac{-dt * v * sth, dt * cth, dt * v * cth, dt * sth, dt, dy.a33, dy.a44};
+}
+
+// Sigma <- A Sigma A^T (Eq. 10, without the GP variance, which the caller adds):
+// B = A Sigma by rows, then Sigma+_ij = sum_n B_in A_jn for i <= j.  Every
+// product-sum is an explicit fused multiply-add, so the rounding does not depend
+// on how the compiler contracts the surrounding code (the split rollout computes
+// the position block apart from the rest and must reproduce it exactly).
+__device__ __forceinline__ void propagate_cov(Cov &c, const StepJac &j) {
+    const float a02 = j.a02, a03 = j.a03, a12 = j.a12, a13 = j.a13, a24 = j.a24, a33 = j.a33, a44 = j.a44;
+    const float b00 = fmaf(a03, c.p03, fmaf(a02, c.p02, c.p00)), b01 = fmaf(a03, c.p13, fmaf(a02, c.p12, c.p01)),
+                b02 = fmaf(a03, c.p23, fmaf(a02, c.p22, c.p02)), b03 = fmaf(a03, c.p33, fmaf(a02, c.p23, c.p03)),
+                b04 = fmaf(a03, c.p34, fmaf(a02, c.p24, c.p04));
+    const float b11 = fmaf(a13, c.p13, fmaf(a12, c.p12, c.p11)), b12 = fmaf(a13, c.p23, fmaf(a12, c.p22, c.p12)),
+                b13 = fmaf(a13, c.p33, fmaf(a12, c.p23, c.p13)), b14 = fmaf(a13, c.p34, fmaf(a12, c.p24, c.p14));
+    const float b22 = fmaf(a24, c.p24, c.p22), b23 = fmaf(a24, c.p34, c.p23), b24 = fmaf(a24, c.p44, c.p24);
+    const float b33 = a33 * c.p33, b34 = a33 * c.p34;
+    const float b44 = a44 * c.p44;
+    c.p00 = fmaf(a03, b03, fmaf(a02, b02, b00));
+    c.p01 = fmaf(a13, b03, fmaf(a12, b02, b01));
+    c.p02 = fmaf(a24, b04, b02);
+    c.p03 = a33 * b03;
+    c.p04 = a44 * b04;
+    c.p11 = fmaf(a13, b13, fmaf(a12, b12, b11));
+    c.p12 = fmaf(a24, b14, b12);
+    c.p13 = a33 * b13;
+    c.p14 = a44 * b14;
+    c.p22 = fmaf(a24, b24, b22);
+    c.p23 = a33 * b23;
+    c.p24 = a44 * b24;
+    c.p33 = a33 * b33;
+    c.p34 = a44 * b34;
+    c.p44 = a44 * b44;
+}
+
+// The position block (Sigma_xx, Sigma_xy, Sigma_yy) of A Sigma A^T alone, by the
+// same operations as propagate_cov; it does not involve the velocity variances'
+// own entries p04, p14, p24, p34, p44.
+__device__ __forceinline__ void propagate_pos_block(const Cov &c, const StepJac &j, float &sa, float &sb,
+                                                    float &sc) {
+    const float a02 = j.a02, a03 = j.a03, a12 = j.a12, a13 = j.a13;
+    const float b00 = fmaf(a03, c.p03, fmaf(a02, c.p02, c.p00)), b01 = fmaf(a03, c.p13, fmaf(a02, c.p12, c.p01)),
+                b02 = fmaf(a03, c.p23, fmaf(a02, c.p22, c.p02)), b03 = fmaf(a03, c.p33, fmaf(a02, c.p23, c.p03));
+    const float b11 = fmaf(a13, c.p13, fmaf(a12, c.p12, c.p11)), b12 = fmaf(a13, c.p23, fmaf(a12, c.p22, c.p12)),
+                b13 = fmaf(a13, c.p33, fmaf(a12, c.p23, c.p13));
+    sa = fmaf(a03, b03, fmaf(a02, b02, b00));
+    sb = fmaf(a13, b03, fmaf(a12, b02, b01));
+    sc = fmaf(a13, b13, fmaf(a12, b12, b11));
+}
+
+// The GP variance s2 of a step into a velocity variance (Eq. 10): p += dt^2 s2.
+__device__ __forceinline__ void add_gp_variance(float &p, float dt, float s2) { p = fmaf(dt * dt, s2, p); }
+
+// Velocities after one explicit Euler step of the dynamic unicycle plus the GP
+// residual means m0, m1 (Eqs. 1, 2, 10).
+__device__ __forceinline__ void advance_velocities(const Dyn &dy, float2 u, float m0, float m1, float &v, float &w) {
+    const float v_old = v, w_old = w;
+    v = v_old + (dy.dt_tau_v * (u.x - v_old) + dy.dt * m0);
+    w = w_old + (dy.dt_tau_w * (u.y - w_old) + dy.dt * m1);
+}
+
+// One wave's share of the polyline (oo = 0) or obstacle (oo = 1) loop at the
+// position (Xs, Ys) and position covariance (sa, sb, sc), for waves wv < LW:
+// the squared distance to segments wv, wv + LW, ... goes to ored[wv][sl], the
+// least tightened obstacle distance over obstacles wv, wv + LW, ... to
+// ored[LW + wv][sl].  Segments and obstacles are wave-uniform (scalar cache).
+template <int LW, int B>
+__device__ __forceinline__ void world_loop(const Geometry &geo, int oo, int wv, int sl, float Xs, float Ys, float sa,
+                                           float sb, float sc, float lmax, float *ored) {
+    if (wv >= LW) return;
+    if (oo == 0) {
+        if (geo.path_kind == 0) return;
+        float best = INFINITY;
+        const const_v4p segs = (const_v4p)geo.seg;
+        const const_fp sinv = (const_fp)geo.seg_inv;
+#pragma unroll 4
+        for (int i = wv; i < geo.P; i += LW) {
+            const v4f sgm = segs[i];
+            const float rx = Xs - sgm.x, ry = Ys - sgm.y;
+            float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
+            t = fminf(fmaxf(t, 0.0f), 1.0f);
+            const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
+            best = fminf(best, ex * ex + ey * ey);
+        }
+        ored[wv * B + sl] = best;
+    } else {
+        float om = INFINITY;
+        const const_v4p obs = (const_v4p)geo.obs;
+#pragma unroll 2
+        for (int j = wv; j < geo.n_obs; j += LW) {
+            const v4f ob = obs[j];
+            om = fminf(om, obstacle_margin(Xs - ob.x, Ys - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
+        }
+        ored[(LW + wv) * B + sl] = om;
+    }
+}
+
+// What a step's cost needs besides the GP variances: the lane deviation dl and
+// tightened half-width rbar (Eqs. 13, 15), the least tightened obstacle
+// distance om (Eqs. 14, 16), the speed error dv and the goal distance dg.
+struct StageIn {
+    float dl, rbar, om, dv, dg;
+};
+
+// Reduces the loop results of ored (written before the contraction's last
+// barrier) and forms the step's StageIn at the position (X, Y) and speed v.
+template <int LW, int B>
+__device__ __forceinline__ StageIn stage_inputs(const Geometry &geo, const CostWeights &cw, const float *ored, int sl,
+                                                float X, float Y, float v, float lmax, float &dgoal_min) {
+    float best_all = INFINITY, om = INFINITY;
+#pragma unroll
+    for (int p = 0; p < LW; ++p) {
+        if (geo.path_kind != 0) best_all = fminf(best_all, ored[p * B + sl]);
+        om = fminf(om, ored[(LW + p) * B + sl]);
+    }
+    StageIn t;
+    if (geo.path_kind == 0) {
+        const float dx = X - geo.cx, dyy = Y - geo.cy;
+        t.dl = fabsf(sqrtf(dx * dx + dyy * dyy) - geo.R);
+    } else {
+        t.dl = sqrtf(best_all);
+    }
+    t.rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
+    t.om = om;
+    t.dv = cw.v_des - v;
+    t.dg = 0.0f;
+    if (cw.w_goal != 0.0f || cw.w_term != 0.0f) {   // goal terms (Eq. 12)
+        const float gx = X - cw.goal_x, gy = Y - cw.goal_y;
+        t.dg = sqrtf(gx * gx + gy * gy);
+        dgoal_min = fminf(dgoal_min, t.dg);
+    }
+    return t;
+}
+
+// Stage cost (Eqs. 11-12 terms) added to the Kahan-compensated sum (S, Sc) of
+// Eq. (5); the lane term is discounted by disc, which then advances.
+__device__ __forceinline__ void add_stage_cost(const CostWeights &cw, const Geometry &geo, const StageIn &t, float s2a,
+                                               float s2b, float &disc, float &S, float &Sc) {
+    float c = cw.w_var * (s2a + s2b) + cw.w_dev * (t.dl * geo.inv_half_width) + cw.w_speed * (t.dv * t.dv);
+    if (t.dl > t.rbar) c += cw.w_lane * disc;
+    if (t.om <= 0.0f) c += cw.w_obs;
+    if (cw.w_goal != 0.0f || cw.w_term != 0.0f) c += cw.w_goal * t.dg;
+    const float yk = c - Sc;
+    const float tk = S + yk;
+    Sc = (tk - S) - yk;
+    S = tk;
+    disc *= cw.discount;
+}
+
+// Per-step trace rows of sample sg (K samples) at step k; var1 < 0 skips the
+// second output's variance, which the split rollout writes one step later.
+__device__ __forceinline__ void write_trace(const gpmppi_trace &tr, int K, int sg, int k, float X, float Y, float th,
+                                            float v, float w, const Cov &P, float m0, float m1, float s20, float s21,
+                                            const StageIn &t, float2 u, bool var1) {
+    const size_t kk = (size_t)k;
+    if (tr.x_d) {
+        float *xd = tr.x_d + (kk + 1) * 5 * K;
+        xd[0 * K + sg] = X;
+        xd[1 * K + sg] = Y;
+        xd[2 * K + sg] = th;
+        xd[3 * K + sg] = v;
+        xd[4 * K + sg] = w;
+    }
+    if (tr.sxy_d) {
+        float *sd = tr.sxy_d + (kk + 1) * 3 * K;
+        sd[0 * K + sg] = P.p00;
+        sd[1 * K + sg] = P.p01;
+        sd[2 * K + sg] = P.p11;
+    }
+    if (tr.gp_mean_d) {
+        tr.gp_mean_d[(kk * 2 + 0) * K + sg] = m0;
+        tr.gp_mean_d[(kk * 2 + 1) * K + sg] = m1;
+    }
+    if (tr.gp_var_d) {
+        tr.gp_var_d[(kk * 2 + 0) * K + sg] = s20;
+        if (var1) tr.gp_var_d[(kk * 2 + 1) * K + sg] = s21;
+    }
+    if (tr.d_lane_d) tr.d_lane_d[kk * K + sg] = t.dl;
+    if (tr.lane_margin_d) tr.lane_margin_d[kk * K + sg] = t.rbar - t.dl;
+    if (tr.obs_margin_d) tr.obs_margin_d[kk * K + sg] = t.om;
+    if (tr.u_d) {
+        tr.u_d[(kk * 2 + 0) * K + sg] = u.x;
+        tr.u_d[(kk * 2 + 1) * K + sg] = u.y;
+    }
+}
+
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
 // problem; called by all threads of a workgroup.
 template <int PREC, int G, int NW = kWaves, int WALK = kWalkAny>
@@ -74,8 +273,7 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
     const Geometry &geo = a.geo;
 
     float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w_ = a.x0[4];
-    float p00 = 0, p01 = 0, p02 = 0, p03 = 0, p04 = 0, p11 = 0, p12 = 0, p13 = 0, p14 = 0, p22 = 0,
-          p23 = 0, p24 = 0, p33 = 0, p34 = 0, p44 = 0;
+    Cov P{};
     float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
     float dgoal_min = INFINITY;
 
@@ -111,41 +309,15 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         float sth, cth;
         sincosf(th, &sth, &cth);
         const float dt = dy.dt;
-        const float a02 = -dt * v * sth, a03 = dt * cth, a12 = dt * v * cth, a13 = dt * sth, a24 = dt;
-        const float a33 = dy.a33, a44 = dy.a44;
-        const float v_old = v, w_old = w_;
+        const StepJac jac = step_jacobian(dy, v, sth, cth);
         X = X + dt * v * cth;
         Y = Y + dt * v * sth;
         th = th + dt * w_;
-        {   // B = A Sigma (rows), then Sigma+_ij = sum_n B_in A_jn for i <= j
-            const float b00 = p00 + a02 * p02 + a03 * p03, b01 = p01 + a02 * p12 + a03 * p13,
-                        b02 = p02 + a02 * p22 + a03 * p23, b03 = p03 + a02 * p23 + a03 * p33,
-                        b04 = p04 + a02 * p24 + a03 * p34;
-            const float b11 = p11 + a12 * p12 + a13 * p13, b12 = p12 + a12 * p22 + a13 * p23,
-                        b13 = p13 + a12 * p23 + a13 * p33, b14 = p14 + a12 * p24 + a13 * p34;
-            const float b22 = p22 + a24 * p24, b23 = p23 + a24 * p34, b24 = p24 + a24 * p44;
-            const float b33 = a33 * p33, b34 = a33 * p34;
-            const float b44 = a44 * p44;
-            p00 = b00 + a02 * b02 + a03 * b03;
-            p01 = b01 + a12 * b02 + a13 * b03;
-            p02 = b02 + a24 * b04;
-            p03 = a33 * b03;
-            p04 = a44 * b04;
-            p11 = b11 + a12 * b12 + a13 * b13;
-            p12 = b12 + a24 * b14;
-            p13 = a33 * b13;
-            p14 = a44 * b14;
-            p22 = b22 + a24 * b24;
-            p23 = a33 * b23;
-            p24 = a44 * b24;
-            p33 = a33 * b33;
-            p34 = a44 * b34;
-            p44 = a44 * b44;
-        }
+        propagate_cov(P, jac);
 
         // ---- chance-constraint geometry at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16); with Step 2
         // tightening the covariance is the nominal sequence's, shared by all samples
-        float sa = p00, sb = p01, sc = p11;
+        float sa = P.p00, sb = P.p01, sc = P.p11;
         if (a.tight_sxy) {
             sa = a.tight_sxy[3 * (k + 1)];
             sb = a.tight_sxy[3 * (k + 1) + 1];
@@ -153,41 +325,10 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         }
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
-        // Loops over polyline segments (during the first output's contraction) and obstacles
-        // (during the second's), run by the first S::lwaves waves, which finish their share of
-        // W first: wave w's squared distance to segments w, w + lwaves, ... and least tightened
-        // distance to obstacles w, w + lwaves, ..., to ored[w] and ored[lwaves + w] (with one
-        // sample group both half-waves hold the same samples and write the same values).
+        // The polyline loop runs during the first output's contraction and the obstacle loop
+        // during the second's, on the first S::lwaves waves, which finish their share of W first
+        // (with one sample group both half-waves hold the same samples and write the same values).
         const float Xs = X, Ys = Y;
-        auto loops = [&](int oo, int wv) {
-            if (wv >= S::lwaves) return;   // wave-uniform: segments and obstacles through the scalar cache
-            if (oo == 0) {
-                if (geo.path_kind == 0) return;
-                float best = INFINITY;
-                const const_v4p segs = (const_v4p)geo.seg;
-                const const_fp sinv = (const_fp)geo.seg_inv;
-#pragma unroll 4
-                for (int i = wv; i < geo.P; i += S::lwaves) {
-                    const v4f sgm = segs[i];
-                    const float rx = Xs - sgm.x, ry = Ys - sgm.y;
-                    float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
-                    t = fminf(fmaxf(t, 0.0f), 1.0f);
-                    const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
-                    best = fminf(best, ex * ex + ey * ey);
-                }
-                ored[wv * S::B + sl] = best;
-            } else {
-                float om = INFINITY;
-                const const_v4p obs = (const_v4p)geo.obs;
-#pragma unroll 2
-                for (int j = wv; j < geo.n_obs; j += S::lwaves) {
-                    const v4f ob = obs[j];
-                    om = fminf(om, obstacle_margin(Xs - ob.x, Ys - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
-                }
-                ored[(S::lwaves + wv) * S::B + sl] = om;
-            }
-        };
-
         float m[2], s2[2];
 #pragma unroll
         for (int oo = 0; oo < 2; ++oo) {
@@ -197,92 +338,237 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
                                  q[3] * a.gp.scale[o][3]};
             m[o] = gp_gen<PREC, G, NW>(a.gp, o, qs, part, sl, lds, pred);
             s2[o] = gp_walk<PREC, G, NW, WALK>(a.gp, o, oo == 0 ? 1 - o : -1, rev, a.rotate, blk, lds, vred, sl,
-                                               [&](int wv) { loops(oo, wv); });
+                                               [&](int wv) {
+                                                   world_loop<S::lwaves, S::B>(geo, oo, wv, sl, Xs, Ys, sa, sb, sc,
+                                                                               lmax, ored);
+                                               });
         }
 
-        // ---- velocities: explicit Euler of the dynamic unicycle plus the GP residual (Eqs. 1, 2,
-        // 10)
-        v = v_old + (dy.dt_tau_v * (u.x - v_old) + dt * m[0]);
-        w_ = w_old + (dy.dt_tau_w * (u.y - w_old) + dt * m[1]);
-
+        advance_velocities(dy, u, m[0], m[1], v, w_);
         // ---- the GP variance into the covariance (Eq. 10)
-        p33 += dt * dt * s2[0];
-        p44 += dt * dt * s2[1];
+        add_gp_variance(P.p33, dt, s2[0]);
+        add_gp_variance(P.p44, dt, s2[1]);
 
-        // the loop parts' partial results were written before the contraction's last barrier
-        float best_all = INFINITY, om = INFINITY;
-#pragma unroll
-        for (int p = 0; p < S::lwaves; ++p) {
-            if (geo.path_kind != 0) best_all = fminf(best_all, ored[p * S::B + sl]);
-            om = fminf(om, ored[(S::lwaves + p) * S::B + sl]);
-        }
-        float dl;
-        if (geo.path_kind == 0) {
-            const float dx = X - geo.cx, dyy = Y - geo.cy;
-            dl = fabsf(sqrtf(dx * dx + dyy * dyy) - geo.R);
-        } else {
-            dl = sqrtf(best_all);
-        }
-        const float rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
-
-        // ---- stage cost (Eqs. 11-12 terms), Kahan-compensated sum (Eq. 5)
-        const float dv = cw.v_des - v;
-        float c = cw.w_var * (s2[0] + s2[1]) + cw.w_dev * (dl * geo.inv_half_width) + cw.w_speed * (dv * dv);
-        if (dl > rbar) c += cw.w_lane * disc;
-        if (om <= 0.0f) c += cw.w_obs;
-        if (cw.w_goal != 0.0f || cw.w_term != 0.0f) {   // goal terms (Eq. 12)
-            const float gx = X - cw.goal_x, gy = Y - cw.goal_y;
-            const float dg = sqrtf(gx * gx + gy * gy);
-            dgoal_min = fminf(dgoal_min, dg);
-            c += cw.w_goal * dg;
-        }
-        {
-            const float yk = c - Sc;
-            const float tk = S_ + yk;
-            Sc = (tk - S_) - yk;
-            S_ = tk;
-        }
-        disc *= cw.discount;
-
-        if (writer) {
-            const gpmppi_trace &tr = a.trace;
-            const size_t kk = (size_t)k;
-            if (tr.x_d) {
-                float *xd = tr.x_d + (kk + 1) * 5 * K;
-                xd[0 * K + sg] = X;
-                xd[1 * K + sg] = Y;
-                xd[2 * K + sg] = th;
-                xd[3 * K + sg] = v;
-                xd[4 * K + sg] = w_;
-            }
-            if (tr.sxy_d) {
-                float *sd = tr.sxy_d + (kk + 1) * 3 * K;
-                sd[0 * K + sg] = p00;
-                sd[1 * K + sg] = p01;
-                sd[2 * K + sg] = p11;
-            }
-            if (tr.gp_mean_d) {
-                tr.gp_mean_d[(kk * 2 + 0) * K + sg] = m[0];
-                tr.gp_mean_d[(kk * 2 + 1) * K + sg] = m[1];
-            }
-            if (tr.gp_var_d) {
-                tr.gp_var_d[(kk * 2 + 0) * K + sg] = s2[0];
-                tr.gp_var_d[(kk * 2 + 1) * K + sg] = s2[1];
-            }
-            if (tr.d_lane_d) tr.d_lane_d[kk * K + sg] = dl;
-            if (tr.lane_margin_d) tr.lane_margin_d[kk * K + sg] = rbar - dl;
-            if (tr.obs_margin_d) tr.obs_margin_d[kk * K + sg] = om;
-            if (tr.u_d) {
-                tr.u_d[(kk * 2 + 0) * K + sg] = u.x;
-                tr.u_d[(kk * 2 + 1) * K + sg] = u.y;
-            }
-        }
+        const StageIn t = stage_inputs<S::lwaves, S::B>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
+        add_stage_cost(cw, geo, t, s2[0], s2[1], disc, S_, Sc);
+        if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m[0], m[1], s2[0], s2[1], t, u, true);
     }
     if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
         const float yk = cw.w_term - Sc;
         S_ = S_ + yk;
     }
     if (writer) a.costs[sg] = S_;
+}
+
+// ---- output split
+// The two GP outputs of one sample block can run on two workgroups of a doubled
+// grid, workgroup 2 blk + r computing output r: where the sample count alone
+// would leave compute units idle, this halves each workgroup's kernel-vector
+// and variance work.  Role 0 carries the full sample state, the covariance, the
+// constraints and the cost; role 1 only the velocities that its queries need.
+// The roles exchange, per step, the two GP means and the second output's
+// variance as 64-bit records (value, tag) stored and loaded at agent scope, one
+// record per sample: a record is valid once its tag names this launch's epoch
+// and the step, so no flag and no store-completion wait is needed.  Slots cycle
+// over four steps (a writer runs at most two steps ahead of a slot's reader).
+// The values reach the same arithmetic as in rollout_block, so the results are
+// bitwise those of the unsplit kernel.  Both workgroups of a block must be
+// resident together (the launcher checks that the whole grid fits at once);
+// every wait is bounded, and a wait that times out yields NaN, which surfaces as
+// non-finite costs.
+
+constexpr int kXchSpin = 1 << 18;   // polls of a record before a wait gives up (~0.3 s)
+
+__device__ __forceinline__ uint32_t xch_tag(uint32_t epoch, int k) {
+    return ((epoch & 0x7FFFFu) << 13) | (uint32_t)(k + 1);   // k + 1 <= 4096 < 2^13
+}
+
+// Lanes 0..31 of the calling wave publish their sample's value.
+__device__ __forceinline__ void xch_put(unsigned long long *rec, int lane, float val, uint32_t tag) {
+    if (lane < 32) {
+        const unsigned long long r = ((unsigned long long)tag << 32) | __float_as_uint(val);
+        __hip_atomic_store(rec + lane, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Every lane of the calling wave waits for the record of sample lane % 32 with
+// this tag and returns its value (NaN once a wait of this wave has timed out).
+__device__ __forceinline__ float xch_get(const unsigned long long *rec, int lane, uint32_t tag, bool &broken) {
+    if (broken) return __builtin_nanf("");
+    unsigned long long r = 0;
+    for (int n = 0;; ++n) {
+        r = __hip_atomic_load(rec + (lane & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__all((uint32_t)(r >> 32) == tag)) break;
+        if (n == kXchSpin) {
+            broken = true;
+            return __builtin_nanf("");
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return __uint_as_float((uint32_t)r);
+}
+
+// Role `role` of sample block blk (one sample group, G = 1); see above.
+template <int PREC, int NW, int WALK>
+__device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int blk, int role, unsigned char *lds,
+                                                    float *pred, float *ored, float *vred, float *xv) {
+    constexpr int G = 1;
+    using S = Shapes<PREC, G, NW>;
+    static_assert(S::B == 32, "exchange records hold one 32-sample group");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int sl = lane % S::B;
+    const int part = 2 * w + (lane >> 5);
+    const int sg = blk * S::B + sl;
+    const int K = a.K;
+    const bool writer = role == 0 && sg < K && w == 0 && lane < S::B;
+    const size_t zs_off = kgroup_bytes<PREC>(a.gp.Mpad);
+
+    NoiseParams np = a.noise;
+    {
+        uint64_t seed = a.seed;
+        if (a.step_counter) seed += (uint64_t)(*a.step_counter);
+        np.key0 = (uint32_t)seed;
+        np.key1 = (uint32_t)(seed >> 32);
+    }
+    const Dyn dy = a.dyn;
+    const CostWeights cw = a.cw;
+    const Geometry &geo = a.geo;
+    const float dt = dy.dt;
+    const uint32_t epoch =
+        __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.xep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    unsigned long long *rec = a.xrec + (size_t)blk * kXchRecPerBlock;
+    auto slot = [&](int k, int kind) { return rec + ((k & 3) * 3 + kind) * 32; };   // kind: m0, m1, s2 of output 1
+    bool broken = false;
+
+    float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w_ = a.x0[4];
+    Cov P{};
+    float S_ = 0.0f, Sc = 0.0f, disc = 1.0f;
+    float dgoal_min = INFINITY;
+    if (writer && a.trace.x_d) {
+        a.trace.x_d[0 * K + sg] = X;
+        a.trace.x_d[1 * K + sg] = Y;
+        a.trace.x_d[2 * K + sg] = th;
+        a.trace.x_d[3 * K + sg] = v;
+        a.trace.x_d[4 * K + sg] = w_;
+    }
+    if (writer && a.trace.sxy_d) {
+        a.trace.sxy_d[0 * K + sg] = 0.0f;
+        a.trace.sxy_d[1 * K + sg] = 0.0f;
+        a.trace.sxy_d[2 * K + sg] = 0.0f;
+    }
+    if constexpr (mfma_gen<PREC>()) {
+        stage_alpha<NW>(a.gp, lds, zs_off);
+    } else {   // the inputs of this role's output, for the whole horizon
+        StagedInputs st;
+        stage_load<PREC, NW>(st, a.gp, role);
+        stage_store<PREC, NW>(st, a.gp, lds, zs_off);
+    }
+
+    StageIn prev{};        // role 0: the previous step's cost inputs, completed by that step's s2 of output 1
+    float s20_prev = 0.0f;
+    for (int k = 0; k < a.T; ++k) {
+        const bool rev = (k & 1) != 0;
+        const uint32_t tag = xch_tag(epoch, k);
+        const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
+        const float qs[4] = {v * a.gp.scale[role][0], w_ * a.gp.scale[role][1], u.x * a.gp.scale[role][2],
+                             u.y * a.gp.scale[role][3]};
+        if (role == 1) {
+            __syncthreads();   // the previous step's k-operand readers are done
+            const float m1 = gp_gen<PREC, G, NW>(a.gp, 1, qs, part, sl, lds, pred);
+            if (w == 0) xch_put(slot(k, 1), lane, m1, tag);
+            const float s21 = gp_walk<PREC, G, NW, WALK>(a.gp, 1, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
+                if (wv == 0) {
+                    const float m0 = xch_get(slot(k, 0), lane, tag, broken);
+                    if (lane < 32) xv[lane] = m0;
+                }
+            });
+            if (w == 0) xch_put(slot(k, 2), lane, s21, tag);
+            advance_velocities(dy, u, xv[sl], m1, v, w_);
+            continue;
+        }
+
+        // ---- role 0: position and heading (Eqs. 1, 10)
+        float sth, cth;
+        sincosf(th, &sth, &cth);
+        const StepJac jac = step_jacobian(dy, v, sth, cth);
+        X = X + dt * v * cth;
+        Y = Y + dt * v * sth;
+        th = th + dt * w_;
+        __syncthreads();
+        const float m0 = gp_gen<PREC, G, NW>(a.gp, 0, qs, part, sl, lds, pred);
+        if (w == 0) xch_put(slot(k, 0), lane, m0, tag);
+
+        // ---- chance-constraint geometry at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16): the position
+        // block of A Sigma A^T does not involve the second output's variance of step k - 1,
+        // which arrives during this step's contraction
+        float sa, sb, sc;
+        propagate_pos_block(P, jac, sa, sb, sc);
+        if (a.tight_sxy) {
+            sa = a.tight_sxy[3 * (k + 1)];
+            sb = a.tight_sxy[3 * (k + 1) + 1];
+            sc = a.tight_sxy[3 * (k + 1) + 2];
+        }
+        const float hh = 0.5f * (sa - sc);
+        const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
+        const float Xs = X, Ys = Y;
+        const float s20 = gp_walk<PREC, G, NW, WALK>(a.gp, 0, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
+            world_loop<S::lwaves, S::B>(geo, 0, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
+            world_loop<S::lwaves, S::B>(geo, 1, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
+            if (wv == 0) {
+                const float m1 = xch_get(slot(k, 1), lane, tag, broken);
+                const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, xch_tag(epoch, k - 1), broken) : 0.0f;
+                if (lane < 32) {
+                    xv[lane] = m1;
+                    xv[32 + lane] = s21p;
+                }
+            }
+        });
+        const float m1 = xv[sl];
+        if (k > 0) {   // step k - 1 completed: its second variance into Sigma_ww, its cost
+            const float s21p = xv[32 + sl];
+            add_gp_variance(P.p44, dt, s21p);
+            add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
+            if (writer && a.trace.gp_var_d) a.trace.gp_var_d[((size_t)(k - 1) * 2 + 1) * K + sg] = s21p;
+        }
+        propagate_cov(P, jac);
+        advance_velocities(dy, u, m0, m1, v, w_);
+        add_gp_variance(P.p33, dt, s20);
+        prev = stage_inputs<S::lwaves, S::B>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
+        s20_prev = s20;
+        if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false);
+    }
+    if (role == 0) {
+        const float s21p = xch_get(slot(a.T - 1, 2), lane, xch_tag(epoch, a.T - 1), broken);
+        add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
+        if (writer && a.trace.gp_var_d) a.trace.gp_var_d[((size_t)(a.T - 1) * 2 + 1) * K + sg] = s21p;
+        if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
+            const float yk = cw.w_term - Sc;
+            S_ = S_ + yk;
+        }
+        if (writer) a.costs[sg] = S_;
+    }
+    // the last workgroup to finish advances the epoch for the next launch
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t n = __hip_atomic_fetch_add(a.xep + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n == gridDim.x - 1) {
+            __hip_atomic_store(a.xep + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.xep, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int PREC, int NW, int WALK>
+__global__ __launch_bounds__(64 * NW) void rollout_split_kernel(RolloutArgs a) {
+    using S = Shapes<PREC, 1, NW>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ float pred[S::rparts * S::B];
+    __shared__ float ored[2 * S::lwaves * S::B];
+    __shared__ float vred[NW * S::B];
+    __shared__ float xv[2 * 32];
+    const int role = __builtin_amdgcn_readfirstlane((int)(blockIdx.x & 1));
+    rollout_block_split<PREC, NW, WALK>(a, blockIdx.x >> 1, role, lds, pred, ored, vred, xv);
 }
 
 template <int PREC, int G, int NW, int WALK>
@@ -402,8 +688,56 @@ static hipError_t launch_rollout_t(const RolloutArgs &a, hipStream_t st) {
                                      : launch_rollout_w<PREC, G, NW, kWalkPairs>(a, st);
 }
 
+// Workgroups of fn (64 NW threads, lds bytes of dynamic LDS) resident at once on the device.
+template <typename F>
+static hipError_t resident_blocks(F *fn, int NW, size_t lds, int &n) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 64 * NW, lds);
+    n = e == hipSuccess ? per_cu * ncu : 0;
+    return e;
+}
+
+template <int PREC, int NW, int WALK>
+static hipError_t split_capacity_w(int Mpad, int &n) {
+    const size_t lds = dyn_lds_bytes<PREC, 1>(Mpad);
+    hipError_t e = set_lds(rollout_split_kernel<PREC, NW, WALK>, lds);
+    if (e != hipSuccess) return e;
+    return resident_blocks(rollout_split_kernel<PREC, NW, WALK>, NW, lds, n);
+}
+
+template <int PREC, int NW>
+static int split_capacity_t(int Mpad) {
+    int n = 0;
+    const hipError_t e = walk_by_rows(Mpad / 32, NW) ? split_capacity_w<PREC, NW, kWalkRows>(Mpad, n)
+                                                    : split_capacity_w<PREC, NW, kWalkPairs>(Mpad, n);
+    return e == hipSuccess ? 32 * (n / 2) : 0;
+}
+
+template <int PREC, int NW, int WALK>
+static hipError_t launch_rollout_split_w(const RolloutArgs &a, hipStream_t st) {
+    if (!a.xrec || !a.xep) return hipErrorInvalidValue;
+    const size_t lds = dyn_lds_bytes<PREC, 1>(a.gp.Mpad);
+    int cap = 0;
+    hipError_t e = split_capacity_w<PREC, NW, WALK>(a.gp.Mpad, cap);
+    if (e != hipSuccess) return e;
+    const int nblk = (a.K + 31) / 32;
+    if (2 * nblk > cap) return hipErrorCooperativeLaunchTooLarge;   // both roles of every block resident together
+    hipLaunchKernelGGL((rollout_split_kernel<PREC, NW, WALK>), dim3(2 * nblk), dim3(64 * NW), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int NW>
+static hipError_t launch_rollout_split_t(const RolloutArgs &a, hipStream_t st) {
+    return walk_by_rows(a.gp.NT, NW) ? launch_rollout_split_w<PREC, NW, kWalkRows>(a, st)
+                                     : launch_rollout_split_w<PREC, NW, kWalkPairs>(a, st);
+}
+
 template <int PREC>
-static hipError_t launch_rollout_p(const RolloutArgs &a, int G, int NW, hipStream_t st) {
+static hipError_t launch_rollout_p(const RolloutArgs &a, int G, int NW, int split, hipStream_t st) {
+    if (split) return NW == 8 ? launch_rollout_split_t<PREC, 8>(a, st) : launch_rollout_split_t<PREC, kWaves>(a, st);
     if (NW == 8) return G == 2 ? launch_rollout_t<PREC, 2, 8>(a, st) : launch_rollout_t<PREC, 1, 8>(a, st);
     return G == 2 ? launch_rollout_t<PREC, 2, kWaves>(a, st) : launch_rollout_t<PREC, 1, kWaves>(a, st);
 }
@@ -446,12 +780,23 @@ hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d,
     }
 }
 
-hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, hipStream_t st) {
-    if (G < 1 || G > groups_for(precision, a.gp.Mpad) || (NW != kWaves && NW != 8)) return hipErrorInvalidValue;
+hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, a.gp.Mpad) || (NW != kWaves && NW != 8) || (split != 0 && split != 1) ||
+        (split && G != 1))
+        return hipErrorInvalidValue;
     switch (precision) {
-        case GPMPPI_FP32: return launch_rollout_p<GPMPPI_FP32>(a, G, NW, st);
-        case GPMPPI_BF16: return launch_rollout_p<GPMPPI_BF16>(a, G, NW, st);
-        default: return launch_rollout_p<GPMPPI_BF16X3>(a, G, NW, st);
+        case GPMPPI_FP32: return launch_rollout_p<GPMPPI_FP32>(a, G, NW, split, st);
+        case GPMPPI_BF16: return launch_rollout_p<GPMPPI_BF16>(a, G, NW, split, st);
+        default: return launch_rollout_p<GPMPPI_BF16X3>(a, G, NW, split, st);
+    }
+}
+
+int rollout_split_capacity(int precision, int Mpad, int NW) {
+    if (NW != kWaves && NW != 8) return 0;
+    switch (precision) {
+        case GPMPPI_FP32: return NW == 8 ? split_capacity_t<GPMPPI_FP32, 8>(Mpad) : split_capacity_t<GPMPPI_FP32, kWaves>(Mpad);
+        case GPMPPI_BF16: return NW == 8 ? split_capacity_t<GPMPPI_BF16, 8>(Mpad) : split_capacity_t<GPMPPI_BF16, kWaves>(Mpad);
+        default: return NW == 8 ? split_capacity_t<GPMPPI_BF16X3, 8>(Mpad) : split_capacity_t<GPMPPI_BF16X3, kWaves>(Mpad);
     }
 }
 

@@ -86,6 +86,9 @@ struct gpmppi_ctx {
     int groups = 1;                  // sample groups of 32 per rollout workgroup (tuned)
     int waves = 4;                   // wave64s per rollout workgroup, 4 or 8 (tuned)
     int rotate = 1;                  // block-dependent start of the walk over W (tuned)
+    int split = 0;                   // 1: the two GP outputs of a sample block on two workgroups (tuned)
+    unsigned long long *xrec = nullptr;   // output-split exchange records [ceil(K/32)][kXchRecPerBlock]
+    uint32_t *xep = nullptr;              // output-split launch epoch and finished-workgroup count
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
     uint4 *zop = nullptr;            // BF16 exponent-product operands per output
@@ -271,6 +274,8 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     a.K = c->params.K;
     a.T = c->params.T;
     a.rotate = c->rotate;
+    a.xrec = c->xrec;
+    a.xep = c->xep;
     a.x0 = x0;
     a.U = U;
     a.costs = costs;
@@ -289,7 +294,7 @@ const float *enqueue_tightening(gpmppi_ctx *c, const float *x0, const float *U, 
     n.noise.sig_v = 0.0f;
     n.noise.sig_w = 0.0f;
     n.trace.sxy_d = c->tight;
-    err = launch_rollout(n, c->params.precision, c->groups, c->waves, st);
+    err = launch_rollout(n, c->params.precision, c->groups, c->waves, c->split, st);
     return c->tight;
 }
 
@@ -373,11 +378,16 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     c->U_scratch = track(dev_alloc<float>((size_t)2 * params->T, st));
     c->cost_scratch = track(dev_alloc<float>((size_t)params->K, st));
     c->tight = track(dev_alloc<float>((size_t)3 * (params->T + 1) + 1, st));
+    const size_t nxrec = (size_t)((params->K + 31) / 32) * kXchRecPerBlock;
+    c->xrec = track(dev_alloc<unsigned long long>(nxrec, st));
+    c->xep = track(dev_alloc<uint32_t>(2, st));
     if (st != GPMPPI_OK) {
         delete c;
         return st;
     }
-    if (hipMemset(c->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMemset(c->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->xrec, 0, nxrec * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->xep, 0, 2 * sizeof(uint32_t)) != hipSuccess) {
         delete c;
         return fail(GPMPPI_E_HIP, "hipMemset failed");
     }
@@ -542,7 +552,7 @@ gpmppi_status gpmppi_rollout(gpmppi_ctx *c, const float *x0_d, const float *U_d,
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, trace, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, c->split, (hipStream_t)stream));
     return GPMPPI_OK;
 }
 
@@ -564,7 +574,7 @@ gpmppi_status gpmppi_step(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     HIP_TRY(e);
     RolloutArgs a = rollout_args(c, x0_d, U_d, seed, costs_d, nullptr, nullptr);
     a.tight_sxy = tight;
-    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, (hipStream_t)stream));
+    HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, c->split, (hipStream_t)stream));
     const UpdateArgs u = update_args(c, costs_d, U_d, seed, U_out_d, weights_d, nullptr);
     HIP_TRY(launch_update(u, (hipStream_t)stream));
     return GPMPPI_OK;
@@ -608,7 +618,7 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t
         HIP_TRY(e);
         RolloutArgs a = rollout_args(c, x_d, U_d, seed0, c->cost_scratch, nullptr, counter);
         a.tight_sxy = tight;
-        HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, s));
+        HIP_TRY(launch_rollout(a, c->params.precision, c->groups, c->waves, c->split, s));
         const UpdateArgs u = update_args(c, c->cost_scratch, U_d, seed0, U_d, nullptr, counter);
         HIP_TRY(launch_update(u, s));
         HIP_TRY(launch_plant_shift(x_d, x_d, U_d, c->params.T, c->dyn, (float)amplitude, counter, x_hist_d,
@@ -717,12 +727,20 @@ int wg_capacity(int precision, int G, int Mpad) {
     return std::max(1, std::min(2, (int)((160 * 1024) / (lds + 4096))));
 }
 
+// Both workgroups of every sample block fit the device at once (output split, one group).
+bool split_admissible(const gpmppi_ctx *c, int waves) {
+    return c->params.K <= rollout_split_capacity(c->params.precision, c->Mpad, waves);
+}
+
 gpmppi_status check_tuning(const gpmppi_tuning *t, int G_max, int wg_max, bool batch) {
     if (!t) return fail(GPMPPI_E_INVALID, "tuning is NULL");
     if (t->waves != 4 && t->waves != 8) return fail(GPMPPI_E_INVALID, "waves must be 4 or 8 (got %d)", t->waves);
     if (t->groups < 1 || t->groups > G_max)
         return fail(GPMPPI_E_INVALID, "groups must lie in [1, %d] here (got %d)", G_max, t->groups);
     if (t->rotate != 0 && t->rotate != 1) return fail(GPMPPI_E_INVALID, "rotate must be 0 or 1");
+    if (t->split != 0 && t->split != 1) return fail(GPMPPI_E_INVALID, "split must be 0 or 1");
+    if (t->split && batch) return fail(GPMPPI_E_INVALID, "batches do not split outputs (split must be 0)");
+    if (t->split && t->groups != 1) return fail(GPMPPI_E_INVALID, "split outputs need groups = 1");
     if (batch) {
         if (t->wg_per_cu < 1 || t->wg_per_cu > wg_max)
             return fail(GPMPPI_E_INVALID, "wg_per_cu must lie in [1, %d] at this shape (got %d)", wg_max,
@@ -788,16 +806,20 @@ gpmppi_status gpmppi_set_tuning(gpmppi_ctx *c, const gpmppi_tuning *t) {
     if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
     gpmppi_status st = check_tuning(t, rollout_groups(c->params.precision, c->Mpad), 2, false);
     if (st != GPMPPI_OK) return st;
+    if (t->split && !split_admissible(c, t->waves))
+        return fail(GPMPPI_E_UNSUPPORTED, "split outputs: the doubled grid of %d workgroups does not fit the device at once",
+                    2 * ((c->params.K + 31) / 32));
     c->groups = t->groups;
     c->rotate = t->rotate;
     c->waves = t->waves;
+    c->split = t->split;
     return GPMPPI_OK;
 }
 
 gpmppi_status gpmppi_get_tuning(const gpmppi_ctx *c, gpmppi_tuning *t) {
     g_last_error.clear();
     if (!c || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
-    *t = gpmppi_tuning{c->groups, c->rotate, 1, 0, c->waves, 0.0};
+    *t = gpmppi_tuning{c->groups, c->rotate, 1, 0, c->waves, c->split, 0.0};
     return GPMPPI_OK;
 }
 
@@ -808,29 +830,33 @@ gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
     hipStream_t st = (hipStream_t)stream;
     const int G_max = rollout_groups(c->params.precision, c->Mpad);
-    const int keep_groups = c->groups, keep_rotate = c->rotate, keep_waves = c->waves;
-    gpmppi_tuning best{c->groups, c->rotate, 1, 0, c->waves, -1.0};
+    const int keep_groups = c->groups, keep_rotate = c->rotate, keep_waves = c->waves, keep_split = c->split;
+    gpmppi_tuning best{c->groups, c->rotate, 1, 0, c->waves, c->split, -1.0};
     for (int G = 1; G <= G_max; ++G)
         for (int rot = 0; rot <= 1; ++rot)
-        for (int nw = 4; nw <= 8; nw += 4) {
-            c->groups = G;
-            c->rotate = rot;
-            c->waves = nw;
-            double ms = 0.0;
-            gpmppi_status r = time_launches(
-                [&]() { return gpmppi_rollout(c, x0_d, U_d, seed, c->cost_scratch, nullptr, stream); }, reps, st,
-                ms);
-            if (r != GPMPPI_OK) {
-                c->groups = keep_groups;
-                c->rotate = keep_rotate;
-                c->waves = keep_waves;
-                return r;
-            }
-            if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, nw, ms};
-        }
+            for (int nw = 4; nw <= 8; nw += 4)
+                for (int sp = 0; sp <= (G == 1 && split_admissible(c, nw) ? 1 : 0); ++sp) {
+                    c->groups = G;
+                    c->rotate = rot;
+                    c->waves = nw;
+                    c->split = sp;
+                    double ms = 0.0;
+                    gpmppi_status r = time_launches(
+                        [&]() { return gpmppi_rollout(c, x0_d, U_d, seed, c->cost_scratch, nullptr, stream); },
+                        reps, st, ms);
+                    if (r != GPMPPI_OK) {
+                        c->groups = keep_groups;
+                        c->rotate = keep_rotate;
+                        c->waves = keep_waves;
+                        c->split = keep_split;
+                        return r;
+                    }
+                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, nw, sp, ms};
+                }
     c->groups = best.groups;
     c->rotate = best.rotate;
     c->waves = best.waves;
+    c->split = best.split;
     if (chosen) *chosen = best;
     return GPMPPI_OK;
 }
@@ -931,7 +957,7 @@ gpmppi_status gpmppi_batch_init(int32_t n, const gpmppi_params params[], const g
     (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     b->cus = std::max(1, b->cus);
     b->wg_per_cu_max = wg_capacity(b->precision, b->G_max, b->Mpad_max);
-    if ((st = batch_install(b, gpmppi_tuning{b->G_max, 1, b->wg_per_cu_max, 0, 4, 0.0})) != GPMPPI_OK) {
+    if ((st = batch_install(b, gpmppi_tuning{b->G_max, 1, b->wg_per_cu_max, 0, 4, 0, 0.0})) != GPMPPI_OK) {
         delete b;
         return st;
     }
@@ -950,7 +976,7 @@ gpmppi_status gpmppi_batch_set_tuning(gpmppi_batch *b, const gpmppi_tuning *t) {
 gpmppi_status gpmppi_batch_get_tuning(const gpmppi_batch *b, gpmppi_tuning *t) {
     g_last_error.clear();
     if (!b || !t) return fail(GPMPPI_E_INVALID, "NULL argument");
-    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0.0};
+    *t = gpmppi_tuning{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0, 0.0};
     return GPMPPI_OK;
 }
 
@@ -960,15 +986,15 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
     if (!b || !x0_d || !U_d) return fail(GPMPPI_E_INVALID, "NULL argument");
     if (reps < 1 || reps > 100) return fail(GPMPPI_E_INVALID, "reps must lie in [1, 100] (got %d)", reps);
     hipStream_t st = (hipStream_t)stream;
-    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0.0};
-    gpmppi_tuning best{0, 0, 0, 0, 4, -1.0};
+    const gpmppi_tuning keep{b->G, b->rotate, b->wg_per_cu, b->order, b->waves, 0, 0.0};
+    gpmppi_tuning best{0, 0, 0, 0, 4, 0, -1.0};
     for (int G = 1; G <= b->G_max; ++G) {
         const int wmax = wg_capacity(b->precision, G, b->Mpad_max);
         for (int rot = 0; rot <= 1; ++rot)
             for (int w = 1; w <= wmax; ++w)
                 for (int ord = 0; ord <= 1; ++ord)
                 for (int nw = 4; nw <= 8; nw += 4) {
-                    const gpmppi_tuning cand{G, rot, w, ord, nw, 0.0};
+                    const gpmppi_tuning cand{G, rot, w, ord, nw, 0, 0.0};
                     gpmppi_status r = batch_install(b, cand);
                     double ms = 0.0;
                     if (r == GPMPPI_OK) {
@@ -989,7 +1015,7 @@ gpmppi_status gpmppi_batch_tune(gpmppi_batch *b, const float *x0_d, const float 
                         (void)batch_install(b, keep);
                         return r;
                     }
-                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, nw, ms};
+                    if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, w, ord, nw, 0, ms};
                 }
     }
     gpmppi_status r = batch_install(b, best);

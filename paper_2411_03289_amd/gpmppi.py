@@ -65,7 +65,8 @@ class gpmppi_trace(ctypes.Structure):
 
 class gpmppi_tuning(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32), ("rotate", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("waves", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("order", ctypes.c_int32), ("waves", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -516,8 +517,8 @@ def gpmppi_tune(ctx: Context, x0, U, seed: int, reps: int = 3, stream=None) -> d
     return t.as_dict()
 
 
-def gpmppi_set_tuning(ctx: Context, groups: int, rotate: int, waves: int = 4):
-    t = gpmppi_tuning(groups, rotate, 1, 0, waves, 0.0)
+def gpmppi_set_tuning(ctx: Context, groups: int, rotate: int, waves: int = 4, split: int = 0):
+    t = gpmppi_tuning(groups, rotate, 1, 0, waves, split, 0.0)
     _check(lib().gpmppi_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -535,7 +536,7 @@ def gpmppi_batch_tune(b: Batch, x0, U, seed: int, reps: int = 2, stream=None) ->
 
 
 def gpmppi_batch_set_tuning(b: Batch, groups: int, rotate: int, wg_per_cu: int, order: int, waves: int = 4):
-    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, waves, 0.0)
+    t = gpmppi_tuning(groups, rotate, wg_per_cu, order, waves, 0, 0.0)
     _check(lib().gpmppi_batch_set_tuning(b.handle, ctypes.byref(t)))
 
 

@@ -137,7 +137,8 @@ def test_batch_validation_without_device(L):
 def test_tuning_struct_and_null_handles(L):
     import ctypes
     assert ctypes.sizeof(B.gpmppi_tuning) == 32
-    t = B.gpmppi_tuning(1, 1, 1, 0, 4, 0.0)
+    assert B.gpmppi_tuning.split.offset == 20 and B.gpmppi_tuning.ms.offset == 24
+    t = B.gpmppi_tuning(1, 1, 1, 0, 4, 0, 0.0)
     for fn in (L.gpmppi_set_tuning, L.gpmppi_batch_set_tuning, L.gpmppi_get_tuning, L.gpmppi_batch_get_tuning):
         assert fn(None, ctypes.byref(t)) == -1
     assert L.gpmppi_tune(None, None, None, 0, 1, None, None) == -1
