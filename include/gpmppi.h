@@ -260,6 +260,12 @@ typedef struct {
  * and writes it, with its time, to *chosen (may be NULL).  Synchronises. */
 gpmppi_status gpmppi_tune(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
                           gpmppi_tuning *chosen, void *stream);
+/* Output split: the number of polls each exchange wait makes before it gives
+ * up and yields NaN (which reaches the costs and the non-finite status flag).
+ * 0 restores the default (2^18 polls, about 0.3 s); a negative value makes
+ * every wait give up at once, so every cost of a split launch is NaN: a hook for
+ * tests of the failure path.  Takes effect from the next launch. */
+gpmppi_status gpmppi_set_exchange_spin(gpmppi_ctx *ctx, int32_t polls);
 /* Installs a shape (wg_per_cu and order are ignored for a context). */
 gpmppi_status gpmppi_set_tuning(gpmppi_ctx *ctx, const gpmppi_tuning *t);
 gpmppi_status gpmppi_get_tuning(const gpmppi_ctx *ctx, gpmppi_tuning *t);

@@ -77,6 +77,7 @@ struct RolloutArgs {
     // and finished-workgroup count [2]; see rollout_block_split
     unsigned long long *xrec;
     uint32_t *xep;
+    int xspin;                      // polls per exchange wait before it gives up; < 0: give up at once
 };
 
 struct UpdateArgs {
@@ -102,6 +103,7 @@ hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, in
 // Largest sample count whose split launch at this shape can be resident at once (0: not admissible).
 int rollout_split_capacity(int precision, int Mpad, int NW);
 constexpr int kXchRecPerBlock = 4 * 3 * 32;   // exchange records per sample block
+constexpr int kXchSpin = 1 << 18;               // default polls of an exchange wait (~0.3 s)
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
                                 int precision, int G, int NW, int Mpad_max, int grid, hipStream_t st);
 hipError_t launch_update_batch(const UpdateArgs *probs_d, const int2 *items_d, int n_items, hipStream_t st);

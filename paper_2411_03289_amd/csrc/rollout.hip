@@ -374,10 +374,8 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 // The values reach the same arithmetic as in rollout_block, so the results are
 // bitwise those of the unsplit kernel.  Both workgroups of a block must be
 // resident together (the launcher checks that the whole grid fits at once);
-// every wait is bounded, and a wait that times out yields NaN, which surfaces as
-// non-finite costs.
-
-constexpr int kXchSpin = 1 << 18;   // polls of a record before a wait gives up (~0.3 s)
+// every wait is bounded (RolloutArgs::xspin polls), and a wait that times out
+// yields NaN, which surfaces as non-finite costs.
 
 __device__ __forceinline__ uint32_t xch_tag(uint32_t epoch, int k) {
     return ((epoch & 0x7FFFFu) << 13) | (uint32_t)(k + 1);   // k + 1 <= 4096 < 2^13
@@ -391,15 +389,18 @@ __device__ __forceinline__ void xch_put(unsigned long long *rec, int lane, float
     }
 }
 
-// Every lane of the calling wave waits for the record of sample lane % 32 with
-// this tag and returns its value (NaN once a wait of this wave has timed out).
-__device__ __forceinline__ float xch_get(const unsigned long long *rec, int lane, uint32_t tag, bool &broken) {
+// Every lane of the calling wave waits, for at most spin polls, for the record
+// of sample lane % 32 with this tag and returns its value (NaN once a wait of
+// this wave has timed out; spin < 0 gives up at once).
+__device__ __forceinline__ float xch_get(const unsigned long long *rec, int lane, uint32_t tag, int spin,
+                                         bool &broken) {
+    if (spin < 0) broken = true;
     if (broken) return __builtin_nanf("");
     unsigned long long r = 0;
     for (int n = 0;; ++n) {
         r = __hip_atomic_load(rec + (lane & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__all((uint32_t)(r >> 32) == tag)) break;
-        if (n == kXchSpin) {
+        if (n == spin) {
             broken = true;
             return __builtin_nanf("");
         }
@@ -440,6 +441,7 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
     unsigned long long *rec = a.xrec + (size_t)blk * kXchRecPerBlock;
     auto slot = [&](int k, int kind) { return rec + ((k & 3) * 3 + kind) * 32; };   // kind: m0, m1, s2 of output 1
     bool broken = false;
+    const int spin = a.xspin;
 
     float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w_ = a.x0[4];
     Cov P{};
@@ -479,7 +481,7 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
             if (w == 0) xch_put(slot(k, 1), lane, m1, tag);
             const float s21 = gp_walk<PREC, G, NW, WALK>(a.gp, 1, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
                 if (wv == 0) {
-                    const float m0 = xch_get(slot(k, 0), lane, tag, broken);
+                    const float m0 = xch_get(slot(k, 0), lane, tag, spin, broken);
                     if (lane < 32) xv[lane] = m0;
                 }
             });
@@ -516,8 +518,8 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
             world_loop<S::lwaves, S::B>(geo, 0, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
             world_loop<S::lwaves, S::B>(geo, 1, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
             if (wv == 0) {
-                const float m1 = xch_get(slot(k, 1), lane, tag, broken);
-                const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, xch_tag(epoch, k - 1), broken) : 0.0f;
+                const float m1 = xch_get(slot(k, 1), lane, tag, spin, broken);
+                const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, xch_tag(epoch, k - 1), spin, broken) : 0.0f;
                 if (lane < 32) {
                     xv[lane] = m1;
                     xv[32 + lane] = s21p;
@@ -539,7 +541,7 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false);
     }
     if (role == 0) {
-        const float s21p = xch_get(slot(a.T - 1, 2), lane, xch_tag(epoch, a.T - 1), broken);
+        const float s21p = xch_get(slot(a.T - 1, 2), lane, xch_tag(epoch, a.T - 1), spin, broken);
         add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
         if (writer && a.trace.gp_var_d) a.trace.gp_var_d[((size_t)(a.T - 1) * 2 + 1) * K + sg] = s21p;
         if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {

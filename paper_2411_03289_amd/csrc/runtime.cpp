@@ -89,6 +89,7 @@ struct gpmppi_ctx {
     int split = 0;                   // 1: the two GP outputs of a sample block on two workgroups (tuned)
     unsigned long long *xrec = nullptr;   // output-split exchange records [ceil(K/32)][kXchRecPerBlock]
     uint32_t *xep = nullptr;              // output-split launch epoch and finished-workgroup count
+    int xspin = kXchSpin;                 // polls per output-split exchange wait
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
     uint4 *zop = nullptr;            // BF16 exponent-product operands per output
@@ -276,6 +277,7 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     a.rotate = c->rotate;
     a.xrec = c->xrec;
     a.xep = c->xep;
+    a.xspin = c->xspin;
     a.x0 = x0;
     a.U = U;
     a.costs = costs;
@@ -813,6 +815,13 @@ gpmppi_status gpmppi_set_tuning(gpmppi_ctx *c, const gpmppi_tuning *t) {
     c->rotate = t->rotate;
     c->waves = t->waves;
     c->split = t->split;
+    return GPMPPI_OK;
+}
+
+gpmppi_status gpmppi_set_exchange_spin(gpmppi_ctx *c, int32_t polls) {
+    g_last_error.clear();
+    if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
+    c->xspin = polls == 0 ? kXchSpin : (polls < 0 ? -1 : polls);
     return GPMPPI_OK;
 }
 

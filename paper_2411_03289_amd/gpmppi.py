@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
         "gpmppi_grad": [vp, vp, vp, u64, f64, i32, vp, vp, vp, vp, vp, vp],
         "gpmppi_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
+        "gpmppi_set_exchange_spin": [vp, i32],
         "gpmppi_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_batch_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
         "gpmppi_batch_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
@@ -520,6 +521,10 @@ def gpmppi_tune(ctx: Context, x0, U, seed: int, reps: int = 3, stream=None) -> d
 def gpmppi_set_tuning(ctx: Context, groups: int, rotate: int, waves: int = 4, split: int = 0):
     t = gpmppi_tuning(groups, rotate, 1, 0, waves, split, 0.0)
     _check(lib().gpmppi_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def gpmppi_set_exchange_spin(ctx: Context, polls: int):
+    _check(lib().gpmppi_set_exchange_spin(ctx.handle, polls))
 
 
 def gpmppi_get_tuning(ctx: Context) -> dict:

@@ -106,6 +106,7 @@ def test_null_arguments_rejected(L):
     assert L.gpmppi_rollout(None, None, None, 0, None, None, None) == -1
     assert L.gpmppi_philox(0, None, 1, None, None) == -1
     assert L.gpmppi_info(None, None, None, None) == -1
+    assert L.gpmppi_set_exchange_spin(None, 0) == -1
     L.gpmppi_destroy(None)
 
 

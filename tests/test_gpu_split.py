@@ -125,3 +125,25 @@ def test_split_admissibility_and_tuner():
     S_b, _ = gpu_rollout(pr, ctx=ctx)
     if chosen["groups"] == 1:
         np.testing.assert_array_equal(S_a, S_b)
+
+
+def test_split_exchange_timeout_yields_nan_and_the_next_launch_is_exact():
+    # the failure path, forced from the host: every exchange wait gives up at once, the
+    # kernel completes, every cost is NaN and the update raises the non-finite flag; the
+    # next launch (default wait) is exact again (records of the failed launch carry its epoch)
+    pr = W.small_problem(K=96, T=8, M=40, n_obs=3, path="eight", seed_data=211, U_scale=1.0)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    B.gpmppi_set_tuning(ctx, 1, 1, 8, 0)
+    U_a, S_a, w_a = gpu_step(pr, ctx=ctx)
+    assert B.gpmppi_status_flags(ctx) == 0
+    B.gpmppi_set_tuning(ctx, 1, 1, 8, 1)
+    B.gpmppi_set_exchange_spin(ctx, -1)
+    _, S_b, _ = gpu_step(pr, ctx=ctx)
+    assert np.all(np.isnan(S_b))
+    assert B.gpmppi_status_flags(ctx) & 1
+    B.gpmppi_set_exchange_spin(ctx, 0)
+    U_c, S_c, w_c = gpu_step(pr, ctx=ctx)
+    np.testing.assert_array_equal(S_c, S_a)
+    np.testing.assert_array_equal(U_c, U_a)
+    np.testing.assert_array_equal(w_c, w_a)
+    assert B.gpmppi_status_flags(ctx) == 0
