@@ -32,6 +32,9 @@ def _case(name):
         pr = W.small_problem(K=80, T=14, M=50, n_obs=7, path="eight", seed_data=91, U_scale=1.0)
         pr.params.update(W.task_params("avoid", goal=(0.3, 0.2)))
         return pr
+    if name == "terrains":         # ensemble weights fold into alpha and the variance scale
+        return W.add_terrains(W.small_problem(K=96, T=12, M=60, n_obs=6, path="eight", seed_data=81, U_scale=1.0),
+                              seed=82, weights=(0.6, 0.25, 0.15))
     if name == "step2":
         pr = W.small_problem(K=80, T=14, M=50, n_obs=7, path="eight", seed_data=91, U_scale=1.0)
         pr.params["tighten"] = 1
@@ -40,7 +43,7 @@ def _case(name):
 
 
 @pytest.mark.parametrize("form", list(FORMS))
-@pytest.mark.parametrize("case", ["c0", "ragged_rows", "pairs", "tiny", "goal", "step2"])
+@pytest.mark.parametrize("case", ["c0", "ragged_rows", "pairs", "tiny", "goal", "step2", "terrains"])
 def test_split_equals_unsplit_bitwise(form, case):
     pr = _case(case)
     prec = FORMS[form]
