@@ -43,8 +43,8 @@ KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd
                   "paper_2411_03289_amd/csrc/device_common.hpp", "paper_2411_03289_amd/csrc/kernels.hpp",
                   "paper_2411_03289_amd/build.py"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "70c6ab6949cf0608d7bf793f8bdd99f4a50a983e301bf06080e81f27285873e9",
-    "bytes": {"fp32": 510872.625 * 1024, "bf16x3": 830568.25 * 1024, "bf16": 18535 * 1024},
+    "sources_sha256": "4c1c70353e54c9991775f0afee7a4155bd164b9b6b793bfd9bb5625f7db4c049",
+    "bytes": {"fp32": 517411.125 * 1024, "bf16x3": 966476.0 * 1024, "bf16": 18532.0 * 1024},
 }
 
 

@@ -365,7 +365,9 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 // grid, workgroup 2 blk + r computing output r: where the sample count alone
 // would leave compute units idle, this halves each workgroup's kernel-vector
 // and variance work.  Role 0 carries the full sample state, the covariance, the
-// constraints and the cost; role 1 only the velocities that its queries need.
+// constraints (both loops dealt over all of its waves, which wait for the other
+// role's exchange anyway) and the cost; role 1 only the velocities that its
+// queries need.
 // The roles exchange, per step, the two GP means and the second output's
 // variance as 64-bit records (value, tag) stored and loaded at agent scope, one
 // record per sample: a record is valid once its tag names this launch's epoch
@@ -515,8 +517,8 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
         const float Xs = X, Ys = Y;
         const float s20 = gp_walk<PREC, G, NW, WALK>(a.gp, 0, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
-            world_loop<S::lwaves, S::B>(geo, 0, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
-            world_loop<S::lwaves, S::B>(geo, 1, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
+            world_loop<NW, S::B>(geo, 0, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
+            world_loop<NW, S::B>(geo, 1, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
             if (wv == 0) {
                 const float m1 = xch_get(slot(k, 1), lane, tag, spin, broken);
                 const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, xch_tag(epoch, k - 1), spin, broken) : 0.0f;
@@ -536,7 +538,7 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         propagate_cov(P, jac);
         advance_velocities(dy, u, m0, m1, v, w_);
         add_gp_variance(P.p33, dt, s20);
-        prev = stage_inputs<S::lwaves, S::B>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
+        prev = stage_inputs<NW, S::B>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
         s20_prev = s20;
         if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false);
     }
@@ -566,7 +568,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_split_kernel(RolloutArgs a) {
     using S = Shapes<PREC, 1, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[S::rparts * S::B];
-    __shared__ float ored[2 * S::lwaves * S::B];
+    __shared__ float ored[2 * NW * S::B];   // both loops on every wave (rollout_block_split)
     __shared__ float vred[NW * S::B];
     __shared__ float xv[2 * 32];
     const int role = __builtin_amdgcn_readfirstlane((int)(blockIdx.x & 1));
