@@ -73,7 +73,7 @@ struct RolloutArgs {
     const float *tight_sxy;         // [T+1][3] Sigma_XY along the nominal sequence, or NULL (per sample)
     gpmppi_trace trace;
     // output split (two workgroups per sample block): exchange records
-    // [nblk][4 slots][3 kinds][32 samples] of (value, tag) and the launch epoch
+    // [nblk][4 slots][4 kinds][32 samples] of (value, tag) and the launch epoch
     // and finished-workgroup count [2]; see rollout_block_split
     unsigned long long *xrec;
     uint32_t *xep;
@@ -102,7 +102,7 @@ int rollout_groups(int precision, int Mpad);
 hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st);
 // Largest sample count whose split launch at this shape can be resident at once (0: not admissible).
 int rollout_split_capacity(int precision, int Mpad, int NW);
-constexpr int kXchRecPerBlock = 4 * 3 * 32;   // exchange records per sample block
+constexpr int kXchRecPerBlock = 4 * 4 * 32;   // exchange records per sample block
 constexpr int kXchSpin = 1 << 18;               // default polls of an exchange wait (~0.3 s)
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,
                                 int precision, int G, int NW, int Mpad_max, int grid, hipStream_t st);

@@ -111,6 +111,17 @@ __device__ __forceinline__ void propagate_pos_block(const Cov &c, const StepJac 
 // The GP variance s2 of a step into a velocity variance (Eq. 10): p += dt^2 s2.
 __device__ __forceinline__ void add_gp_variance(float &p, float dt, float s2) { p = fmaf(dt * dt, s2, p); }
 
+// Position and heading after one explicit Euler step (Eqs. 1, 10), as explicit
+// fused multiply-adds (both roles of the split rollout integrate them and must
+// agree bit for bit).
+__device__ __forceinline__ void advance_pose(const Dyn &dy, float v, float w, float sth, float cth, float &X, float &Y,
+                                             float &th) {
+    const float dv = dy.dt * v;
+    X = fmaf(dv, cth, X);
+    Y = fmaf(dv, sth, Y);
+    th = fmaf(dy.dt, w, th);
+}
+
 // Velocities after one explicit Euler step of the dynamic unicycle plus the GP
 // residual means m0, m1 (Eqs. 1, 2, 10).
 __device__ __forceinline__ void advance_velocities(const Dyn &dy, float2 u, float m0, float m1, float &v, float &w) {
@@ -164,13 +175,14 @@ struct StageIn {
 
 // Reduces the loop results of ored (written before the contraction's last
 // barrier) and forms the step's StageIn at the position (X, Y) and speed v.
-template <int LW, int B>
+// POLY = false: the polyline part is left to the caller (dl = 0 on a polyline).
+template <int LW, int B, bool POLY = true>
 __device__ __forceinline__ StageIn stage_inputs(const Geometry &geo, const CostWeights &cw, const float *ored, int sl,
                                                 float X, float Y, float v, float lmax, float &dgoal_min) {
     float best_all = INFINITY, om = INFINITY;
 #pragma unroll
     for (int p = 0; p < LW; ++p) {
-        if (geo.path_kind != 0) best_all = fminf(best_all, ored[p * B + sl]);
+        if (POLY && geo.path_kind != 0) best_all = fminf(best_all, ored[p * B + sl]);
         om = fminf(om, ored[(LW + p) * B + sl]);
     }
     StageIn t;
@@ -178,7 +190,7 @@ __device__ __forceinline__ StageIn stage_inputs(const Geometry &geo, const CostW
         const float dx = X - geo.cx, dyy = Y - geo.cy;
         t.dl = fabsf(sqrtf(dx * dx + dyy * dyy) - geo.R);
     } else {
-        t.dl = sqrtf(best_all);
+        t.dl = POLY ? sqrtf(best_all) : 0.0f;
     }
     t.rbar = geo.half_width - geo.c_p * sqrtf(fmaxf(lmax, 0.0f));
     t.om = om;
@@ -207,11 +219,12 @@ __device__ __forceinline__ void add_stage_cost(const CostWeights &cw, const Geom
     disc *= cw.discount;
 }
 
-// Per-step trace rows of sample sg (K samples) at step k; var1 < 0 skips the
-// second output's variance, which the split rollout writes one step later.
+// Per-step trace rows of sample sg (K samples) at step k; var1 = false skips
+// the second output's variance and lane = false the lane rows, which the split
+// rollout writes one step later (write_deferred_trace).
 __device__ __forceinline__ void write_trace(const gpmppi_trace &tr, int K, int sg, int k, float X, float Y, float th,
                                             float v, float w, const Cov &P, float m0, float m1, float s20, float s21,
-                                            const StageIn &t, float2 u, bool var1) {
+                                            const StageIn &t, float2 u, bool var1, bool lane = true) {
     const size_t kk = (size_t)k;
     if (tr.x_d) {
         float *xd = tr.x_d + (kk + 1) * 5 * K;
@@ -235,13 +248,22 @@ __device__ __forceinline__ void write_trace(const gpmppi_trace &tr, int K, int s
         tr.gp_var_d[(kk * 2 + 0) * K + sg] = s20;
         if (var1) tr.gp_var_d[(kk * 2 + 1) * K + sg] = s21;
     }
-    if (tr.d_lane_d) tr.d_lane_d[kk * K + sg] = t.dl;
-    if (tr.lane_margin_d) tr.lane_margin_d[kk * K + sg] = t.rbar - t.dl;
+    if (lane && tr.d_lane_d) tr.d_lane_d[kk * K + sg] = t.dl;
+    if (lane && tr.lane_margin_d) tr.lane_margin_d[kk * K + sg] = t.rbar - t.dl;
     if (tr.obs_margin_d) tr.obs_margin_d[kk * K + sg] = t.om;
     if (tr.u_d) {
         tr.u_d[(kk * 2 + 0) * K + sg] = u.x;
         tr.u_d[(kk * 2 + 1) * K + sg] = u.y;
     }
+}
+
+// The rows write_trace(..., false, false) left out: the second variance and the lane rows.
+__device__ __forceinline__ void write_deferred_trace(const gpmppi_trace &tr, int K, int sg, int k, float s21,
+                                                     const StageIn &t) {
+    const size_t kk = (size_t)k;
+    if (tr.gp_var_d) tr.gp_var_d[(kk * 2 + 1) * K + sg] = s21;
+    if (tr.d_lane_d) tr.d_lane_d[kk * K + sg] = t.dl;
+    if (tr.lane_margin_d) tr.lane_margin_d[kk * K + sg] = t.rbar - t.dl;
 }
 
 // The rollout of sample block blk (samples blk * B .. blk * B + B - 1) of one
@@ -310,9 +332,7 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
         sincosf(th, &sth, &cth);
         const float dt = dy.dt;
         const StepJac jac = step_jacobian(dy, v, sth, cth);
-        X = X + dt * v * cth;
-        Y = Y + dt * v * sth;
-        th = th + dt * w_;
+        advance_pose(dy, v, w_, sth, cth, X, Y, th);
         propagate_cov(P, jac);
 
         // ---- chance-constraint geometry at (x_{k+1}, Sigma_{k+1}) (Eqs. 13-16); with Step 2
@@ -365,11 +385,11 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 // grid, workgroup 2 blk + r computing output r: where the sample count alone
 // would leave compute units idle, this halves each workgroup's kernel-vector
 // and variance work.  Role 0 carries the full sample state, the covariance, the
-// constraints (both loops dealt over all of its waves, which wait for the other
-// role's exchange anyway) and the cost; role 1 only the velocities that its
-// queries need.
-// The roles exchange, per step, the two GP means and the second output's
-// variance as 64-bit records (value, tag) stored and loaded at agent scope, one
+// obstacle loop and the cost; role 1 the pose and velocities that its queries
+// and the polyline loop need.  Both loops are dealt over all of a role's waves.
+// The roles exchange, per step, the two GP means, the second output's variance
+// and the squared distance to the polyline as 64-bit records (value, tag)
+// stored and loaded at agent scope, one
 // record per sample: a record is valid once its tag names this launch's epoch
 // and the step, so no flag and no store-completion wait is needed.  Slots cycle
 // over four steps (a writer runs at most two steps ahead of a slot's reader).
@@ -441,7 +461,8 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
     const uint32_t epoch =
         __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.xep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     unsigned long long *rec = a.xrec + (size_t)blk * kXchRecPerBlock;
-    auto slot = [&](int k, int kind) { return rec + ((k & 3) * 3 + kind) * 32; };   // kind: m0, m1, s2 of output 1
+    // kind: m0, m1, s2 of output 1, squared polyline distance at x_{k+1}
+    auto slot = [&](int k, int kind) { return rec + ((k & 3) * 4 + kind) * 32; };
     bool broken = false;
     const int spin = a.xspin;
 
@@ -477,28 +498,37 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
         const float qs[4] = {v * a.gp.scale[role][0], w_ * a.gp.scale[role][1], u.x * a.gp.scale[role][2],
                              u.y * a.gp.scale[role][3]};
+        float sth, cth;
+        sincosf(th, &sth, &cth);
         if (role == 1) {
-            __syncthreads();   // the previous step's k-operand readers are done
+            advance_pose(dy, v, w_, sth, cth, X, Y, th);
+            const float Xs = X, Ys = Y;
+            __syncthreads();   // the previous step's k-operand and loop-result readers are done
             const float m1 = gp_gen<PREC, G, NW>(a.gp, 1, qs, part, sl, lds, pred);
             if (w == 0) xch_put(slot(k, 1), lane, m1, tag);
             const float s21 = gp_walk<PREC, G, NW, WALK>(a.gp, 1, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
+                world_loop<NW, S::B>(geo, 0, wv, sl, Xs, Ys, 0.0f, 0.0f, 0.0f, 0.0f, ored);
                 if (wv == 0) {
                     const float m0 = xch_get(slot(k, 0), lane, tag, spin, broken);
                     if (lane < 32) xv[lane] = m0;
                 }
             });
-            if (w == 0) xch_put(slot(k, 2), lane, s21, tag);
+            if (w == 0) {
+                xch_put(slot(k, 2), lane, s21, tag);
+                if (geo.path_kind != 0) {
+                    float best = INFINITY;
+#pragma unroll
+                    for (int p = 0; p < NW; ++p) best = fminf(best, ored[p * S::B + sl]);
+                    xch_put(slot(k, 3), lane, best, tag);
+                }
+            }
             advance_velocities(dy, u, xv[sl], m1, v, w_);
             continue;
         }
 
         // ---- role 0: position and heading (Eqs. 1, 10)
-        float sth, cth;
-        sincosf(th, &sth, &cth);
         const StepJac jac = step_jacobian(dy, v, sth, cth);
-        X = X + dt * v * cth;
-        Y = Y + dt * v * sth;
-        th = th + dt * w_;
+        advance_pose(dy, v, w_, sth, cth, X, Y, th);
         __syncthreads();
         const float m0 = gp_gen<PREC, G, NW>(a.gp, 0, qs, part, sl, lds, pred);
         if (w == 0) xch_put(slot(k, 0), lane, m0, tag);
@@ -517,35 +547,41 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
         const float Xs = X, Ys = Y;
         const float s20 = gp_walk<PREC, G, NW, WALK>(a.gp, 0, -1, rev, a.rotate, blk, lds, vred, sl, [&](int wv) {
-            world_loop<NW, S::B>(geo, 0, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
             world_loop<NW, S::B>(geo, 1, wv, sl, Xs, Ys, sa, sb, sc, lmax, ored);
             if (wv == 0) {
                 const float m1 = xch_get(slot(k, 1), lane, tag, spin, broken);
-                const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, xch_tag(epoch, k - 1), spin, broken) : 0.0f;
+                const uint32_t tp = xch_tag(epoch, k - 1);
+                const float s21p = k > 0 ? xch_get(slot(k - 1, 2), lane, tp, spin, broken) : 0.0f;
+                const float bestp =
+                    k > 0 && geo.path_kind != 0 ? xch_get(slot(k - 1, 3), lane, tp, spin, broken) : 0.0f;
                 if (lane < 32) {
                     xv[lane] = m1;
                     xv[32 + lane] = s21p;
+                    xv[64 + lane] = bestp;
                 }
             }
         });
         const float m1 = xv[sl];
-        if (k > 0) {   // step k - 1 completed: its second variance into Sigma_ww, its cost
+        if (k > 0) {   // step k - 1 completed: its second variance into Sigma_ww, its lane distance, its cost
             const float s21p = xv[32 + sl];
             add_gp_variance(P.p44, dt, s21p);
+            if (geo.path_kind != 0) prev.dl = sqrtf(xv[64 + sl]);
             add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
-            if (writer && a.trace.gp_var_d) a.trace.gp_var_d[((size_t)(k - 1) * 2 + 1) * K + sg] = s21p;
+            if (writer) write_deferred_trace(a.trace, K, sg, k - 1, s21p, prev);
         }
         propagate_cov(P, jac);
         advance_velocities(dy, u, m0, m1, v, w_);
         add_gp_variance(P.p33, dt, s20);
-        prev = stage_inputs<NW, S::B>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
+        prev = stage_inputs<NW, S::B, false>(geo, cw, ored, sl, X, Y, v, lmax, dgoal_min);
         s20_prev = s20;
-        if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false);
+        if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false, false);
     }
     if (role == 0) {
-        const float s21p = xch_get(slot(a.T - 1, 2), lane, xch_tag(epoch, a.T - 1), spin, broken);
+        const uint32_t tl = xch_tag(epoch, a.T - 1);
+        const float s21p = xch_get(slot(a.T - 1, 2), lane, tl, spin, broken);
+        if (geo.path_kind != 0) prev.dl = sqrtf(xch_get(slot(a.T - 1, 3), lane, tl, spin, broken));
         add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
-        if (writer && a.trace.gp_var_d) a.trace.gp_var_d[((size_t)(a.T - 1) * 2 + 1) * K + sg] = s21p;
+        if (writer) write_deferred_trace(a.trace, K, sg, a.T - 1, s21p, prev);
         if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
             const float yk = cw.w_term - Sc;
             S_ = S_ + yk;
@@ -570,7 +606,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_split_kernel(RolloutArgs a) {
     __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[2 * NW * S::B];   // both loops on every wave (rollout_block_split)
     __shared__ float vred[NW * S::B];
-    __shared__ float xv[2 * 32];
+    __shared__ float xv[3 * 32];
     const int role = __builtin_amdgcn_readfirstlane((int)(blockIdx.x & 1));
     rollout_block_split<PREC, NW, WALK>(a, blockIdx.x >> 1, role, lds, pred, ored, vred, xv);
 }
