@@ -59,7 +59,7 @@ typedef enum {
 
 typedef struct gpmppi_ctx gpmppi_ctx;   /* opaque; owns every device buffer it allocates */
 
-/* One residual GP (Sec. III-A: one GP per velocity output; Sec. IV-A: input
+/* One residual GP (Sec. III-A: one GP per velocity output; Sec. V-A: input
  * (v, w, v_cmd, w_cmd)).  Squared-exponential ARD covariance
  * k(a,b) = exp(2 log_sf) exp(-1/2 sum_d (a_d-b_d)^2 exp(-2 log_ell[d])),
  * observation noise variance exp(2 log_sn). */
@@ -72,7 +72,7 @@ typedef struct {
     double log_sn;
 } gpmppi_gp;
 
-/* Circular obstacles (Sec. III-C: obstacles are approximated by circles). */
+/* Circular obstacles (Sec. IV-C: obstacles are approximated by circles). */
 typedef struct {
     int32_t n;                  /* 0 <= n <= 4096 */
     const double *xyr;          /* [n][3] (centre x, centre y, radius > 0), host; may be NULL if n == 0 */

@@ -12,7 +12,7 @@ methods it relies on; every function cites the passage it follows:
                   (Salmon et al., SC'11) and the Box-Muller transform
                   -> Alg. 1, Step 1 ("Sample eps^s ~ N(0, Sigma_sim)"), Eq. (8)
   gp.py           exact GP regression (Rasmussen & Williams, Alg. 2.1) with
-                  the SE-ARD kernel -> Sec. III-A, Eq. (3), Sec. IV-A
+                  the SE-ARD kernel -> Sec. III-A, Eq. (3), Sec. V-A
   dynamics.py     dynamic unicycle and first-order covariance propagation
                   -> Eqs. (1), (2), (6), (10)
   constraints.py  lane and obstacle chance-constraint tightening

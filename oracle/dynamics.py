@@ -63,7 +63,7 @@ def covariance_step(Sigma, A, s2, dt):
 def plant_step(x, u, dt, tau_v, tau_w, amplitude=0.3):
     """Synthetic closed-loop plant: the nominal Euler step plus the residual
     amplitude * sin(v w) on both velocity derivatives, without noise.  It
-    stands in for the learned ground-truth velocity model of Sec. IV-A."""
+    stands in for the learned ground-truth velocity model of Sec. V-A."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     r = amplitude * np.sin(x[:, 3] * x[:, 4])
     return euler_step(x, np.atleast_2d(u), np.stack([r, r], axis=1), dt, tau_v, tau_w)

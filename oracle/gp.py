@@ -1,7 +1,7 @@
 """Exact GP regression for the velocity residuals (test infrastructure only).
 
 Sec. III-A trains one GP per velocity output on the residual between measured
-and nominal velocities; Sec. IV-A gives its input (v, w, v_cmd, w_cmd) and a
+and nominal velocities; Sec. V-A gives its input (v, w, v_cmd, w_cmd) and a
 GPyTorch batch GP.  Eq. (3) uses each GP's predictive mean and covariance.
 
 The oracle follows Rasmussen & Williams, "Gaussian Processes for Machine

@@ -6,7 +6,7 @@ and one combined stage cost built from the terms of Eqs. (11) and (12).
 
 For every sample s and step k = 0 .. T-1:
   u = clip(U_k + eps_k^s)                          Alg. 1 Step 1, Eq. (8)
-  q = (v_k, w_k, u_v, u_w)                         Sec. IV-A GP input
+  q = (v_k, w_k, u_v, u_w)                         Sec. V-A GP input
   (m_o, s2_o) = GP_o(q), o in {v, w}               Eq. (3), one terrain
   x_{k+1} = Euler(x_k, u, m)                       Eqs. (1), (2), (10)
   Sigma_{k+1} = A Sigma_k A^T + dt^2 diag(0,0,0,s2)  Eq. (10)

@@ -1,6 +1,6 @@
 // Once-per-GP-update build of each residual GP in FP64 on the GPU
 // (Rasmussen & Williams Alg. 2.1 with the explicit inverse factor):
-//   A = K(Z, Z) + sn^2 I         SE-ARD covariance (Sec. III-A, Sec. IV-A)
+//   A = K(Z, Z) + sn^2 I         SE-ARD covariance (Sec. III-A, Sec. V-A)
 //   L = chol(A)                  blocked left-looking Cholesky, 32x32 tiles
 //   W = L^-1                     block-column forward substitution
 //   alpha = W^T (W y) = A^-1 y

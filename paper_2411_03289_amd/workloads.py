@@ -8,9 +8,9 @@ FP64 oracle can be fed from it without sharing code.
 
 The workloads stand in for the paper's data, which is not available: the GP
 in the paper is trained on 300 shared points with 4-d inputs (current v, w and
-commanded v, w) and residual velocity outputs (Sec. IV-A), obstacles are
-circles (Sec. III-C, Eq. 15-16) and the tracks are circles and closed curves
-driven at 2 m/s (Sec. IV-A).
+commanded v, w) and residual velocity outputs (Sec. V-A), obstacles are
+circles (Sec. IV-C, Eqs. 15-16) and the tracks are circles and closed curves
+driven at 2 m/s (Sec. V-A).
 
 All draws use numpy's PCG64 with an explicit seed, in a fixed order:
   1. for output o in (v, w): Z_o ~ U[-2, 2]^(N x 4), then e_o ~ N(0, 0.05^2)^N;
@@ -39,7 +39,7 @@ DEFAULT_PARAMS = dict(
 
 
 def task_params(task: str, goal=(8.0, 0.0)) -> dict:
-    """Weight presets switching between the paper's two tasks (Sec. III-B):
+    """Weight presets switching between the paper's two tasks (Sec. IV-B):
     path tracking (Eq. 11 terms) or obstacle avoidance towards a goal (Eq. 12)."""
     if task == "track":
         return dict(w_var=1.0, w_dev=0.5, w_lane=1.0, w_speed=0.1, w_obs=0.0, w_goal=0.0, w_term=0.0)
