@@ -261,7 +261,8 @@ typedef struct {
 gpmppi_status gpmppi_tune(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
                           gpmppi_tuning *chosen, void *stream);
 /* Output split: the number of polls each exchange wait makes before it gives
- * up and yields NaN (which reaches the costs and the non-finite status flag).
+ * up and yields NaN (which reaches the costs and the non-finite status flag)
+ * and sets GPMPPI_FLAG_EXCHANGE_TIMEOUT.
  * 0 restores the default (2^18 polls, about 0.3 s); a negative value makes
  * every wait give up at once, so every cost of a split launch is NaN: a hook for
  * tests of the failure path.  Takes effect from the next launch. */
@@ -320,8 +321,13 @@ void gpmppi_batch_destroy(gpmppi_batch *b);
 gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uint32_t *out_d,
                             void *stream);
 
-/* Reads and clears the context's device status bits (bit 0: a non-finite
- * cost was seen by a weights/update call).  Synchronises the device. */
+/* Reads and clears the context's device status bits:
+ *   GPMPPI_FLAG_NONFINITE         a weights/update call saw a non-finite cost;
+ *   GPMPPI_FLAG_EXCHANGE_TIMEOUT  an exchange wait of an output-split rollout
+ *                                 gave up (its samples' costs are NaN).
+ * Synchronises the device. */
+#define GPMPPI_FLAG_NONFINITE 1u
+#define GPMPPI_FLAG_EXCHANGE_TIMEOUT 2u
 gpmppi_status gpmppi_status_flags(gpmppi_ctx *ctx, uint32_t *flags);
 
 /* Derived scalars of a context: M_pad (M rounded up to a multiple of 64),

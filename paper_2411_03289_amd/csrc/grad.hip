@@ -24,11 +24,15 @@
 // matrix cores); with beta_j = k_j (-mbar alpha_j + 2 s2bar r_j):
 //   dq_d        = 2 ln2 s_d sum_j beta_j (qs_d - zs_jd)
 //   d log ell_d = -2 ln2 sum_j beta_j (qs_d - zs_jd)^2       (through k)
-//   d log sf    = -2 sum_j beta_j + 2 sf^2 s2bar             (through k, sf^2)
-// and the dependence through A: sum_ij (P_ij - b_i alpha_j) dA_ij/dtheta with
-// b = sum mbar r and P = sum s2bar r r^T over all sample-steps.  b is summed in
-// registers; P is formed by grad_syrk_kernel from the stored r (FP32
-// [T K][Mpad] per output) and contracted on the fly with dA/dtheta.
+// and the length-scales' dependence through A: sum_ij (P_ij - b_i alpha_j)
+// dA_ij/dlog ell_d with b = sum mbar r and P = sum s2bar r r^T over all
+// sample-steps.  b is summed in registers; P is formed by grad_syrk_kernel from
+// the stored r (FP32 [T K][Mpad] per output) and contracted on the fly.
+// The signal variance scales k and K(Z, Z) alike (dA/dlog sf = 2 (A - sn^2 I)),
+// so with A r = k and A alpha = y its total derivative folds into per-sample
+// terms in which the large parts through k and through A^-1 cancel exactly:
+//   d log sf    = 2 s2bar (s2 - sn^2 - sn^2 |r|^2) + 2 sn^2 mbar r^T alpha
+// (s2 - sn^2 = sf^2 - k^T r, the latent variance of the forward pass).
 #include "adjoint_step.hpp"
 #include "gp_tiles.hpp"
 
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     __shared__ float vred[kWaves * kB];
     __shared__ float vb[kParts * kB], vo[kParts * kB];
     __shared__ int ib[kParts * kB], io[kParts * kB];
-    __shared__ __align__(16) float gred[9 * kParts * kB];
+    __shared__ __align__(16) float gred[11 * kParts * kB];
     __shared__ float mb_s[2][kB], sb_s[2][kB], ub_s[2][kB];
 
     const int tid = threadIdx.x;
@@ -369,6 +373,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             for (int i = 0; i < 15; ++i) pk[i] = e0[(5 + i) * kB];
             const float ux = e0[20 * kB], uy = e0[21 * kB];
             const float flag[2] = {e0[26 * kB], e0[27 * kB]};
+            const float s2k[2] = {e0[24 * kB], e0[25 * kB]};
 
             float x1[5], p1[15], xk[5];
 #pragma unroll
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                 // per-sample sums over this part's points
                 const float4 *zs = reinterpret_cast<const float4 *>(lds + kgroup_bytes<GPMPPI_FP32>(Mpad));
                 const float *al = reinterpret_cast<const float *>(zs + Mpad);
-                float Sb = 0.0f, Sd[4] = {0, 0, 0, 0}, Sdd[4] = {0, 0, 0, 0};
+                float Sd[4] = {0, 0, 0, 0}, Sdd[4] = {0, 0, 0, 0}, Srr = 0.0f, Sra = 0.0f;
                 for (int c = part; c < (Mpad >> 3); c += kParts) {
                     const float4 *Kp = reinterpret_cast<const float4 *>(lds) + (size_t)c * 64;
                     const float4 lo = Kp[sl], hi = Kp[32 + sl];
@@ -421,9 +426,11 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                     for (int e = 0; e < 8; ++e) {
                         const int j = 8 * c + e;
                         const float4 z = zs[j];
-                        const float beta = kv[e] * (2.0f * sbo * rb[sl * (Mpad + 1) + j] - mb[o] * al[j]);
+                        const float rj = rb[sl * (Mpad + 1) + j];
+                        const float beta = kv[e] * (2.0f * sbo * rj - mb[o] * al[j]);
                         const float d0 = qs[0] - z.x, d1 = qs[1] - z.y, d2 = qs[2] - z.z, d3 = qs[3] - z.w;
-                        Sb += beta;
+                        Srr = fmaf(rj, rj, Srr);
+                        Sra = fmaf(rj, al[j], Sra);
                         Sd[0] = fmaf(beta, d0, Sd[0]);
                         Sd[1] = fmaf(beta, d1, Sd[1]);
                         Sd[2] = fmaf(beta, d2, Sd[2]);
@@ -434,12 +441,13 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                         Sdd[3] = fmaf(beta * d3, d3, Sdd[3]);
                     }
                 }
-                gred[(0 * kParts + part) * kB + sl] = Sb;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     gred[((1 + d) * kParts + part) * kB + sl] = Sd[d];
                     gred[((5 + d) * kParts + part) * kB + sl] = Sdd[d];
                 }
+                gred[(9 * kParts + part) * kB + sl] = Srr;
+                gred[(10 * kParts + part) * kB + sl] = Sra;
                 // b += sum_s mbar_s r_s over this thread's points; the r rows for P
                 for (int jj = 0; jj < 2; ++jj) {
                     const int j = tid + kThreads * jj;
@@ -458,9 +466,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                 }
                 if (writer && valid) a.Gw[(size_t)o * T * K + (size_t)k * K + sg] = sbo;
                 __syncthreads();
-                float tot[9];
+                float tot[11];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
+                for (int i = 1; i < 11; ++i) {
                     float sum = 0.0f;
 #pragma unroll
                     for (int pp = 0; pp < kParts; ++pp) sum += gred[(i * kParts + pp) * kB + sl];
@@ -471,7 +479,11 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                     qb[d] += 2.0f * kLn2 * g.scale[o][d] * tot[1 + d];
                     hyp[o][d] += (double)(-2.0f * kLn2 * tot[5 + d]);
                 }
-                hyp[o][4] += (double)(-2.0f * tot[0] + 2.0f * g.sf2[o] * sbo);
+                {   // log sf: the folded per-sample terms (k and A^-1 parts cancelled)
+                    const double sn2 = (double)g.sn2[o];
+                    hyp[o][4] += 2.0 * (double)sbo * (((double)s2k[o] - sn2) - sn2 * (double)tot[9]) +
+                                 2.0 * sn2 * (double)mb[o] * (double)tot[10];
+                }
             }
             vbk += qb[0];
             wbk += qb[1];
@@ -522,10 +534,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 }
 
 
-// dA_ij / dtheta contracted with a weight c_ij, theta = (log ell_0..3, log sf):
-// K_ij = exp2(c2 - |zs_i - zs_j|^2); dA/dlog ell_d = K 2 ln2 (zs_id - zs_jd)^2,
-// dA/dlog sf = 2 K (the sn^2 I part does not depend on them).
-__device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const float4 &zj, float c2, double acc[5]) {
+// dA_ij / dlog ell_d contracted with a weight c_ij: K_ij = exp2(c2 - |zs_i - zs_j|^2),
+// dA/dlog ell_d = K 2 ln2 (zs_id - zs_jd)^2 (the sn^2 I part does not depend on it).
+__device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const float4 &zj, float c2, double acc[4]) {
     const float d0 = zi.x - zj.x, d1 = zi.y - zj.y, d2 = zi.z - zj.z, d3 = zi.w - zj.w;
     const float e0 = d0 * d0, e1 = d1 * d1, e2 = d2 * d2, e3 = d3 * d3;
     const float Kij = __builtin_amdgcn_exp2f(c2 - (e0 + e1 + e2 + e3));
@@ -535,7 +546,6 @@ __device__ __forceinline__ void dA_contract(float cval, const float4 &zi, const 
     acc[1] += (double)(c2l * e1);
     acc[2] += (double)(c2l * e2);
     acc[3] += (double)(c2l * e3);
-    acc[4] += (double)(2.0f * ck);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -545,13 +555,13 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // P = sum_n g_n r_n r_n^T over rows n in [n0, n1) of one output, for one
-// 128 x 128 block (bi <= bj) of the Mpad x Mpad result, contracted with dA/dtheta:
-// ppart[((o * npairs + pair) * nsplit + split) * 5 + theta].  Wave w owns the
+// 128 x 128 block (bi <= bj) of the Mpad x Mpad result, contracted with dA/dlog ell:
+// ppart[((o * npairs + pair) * nsplit + split) * 4 + d].  Wave w owns the
 // 32 x 32 tiles (2 (w >> 1) + {0, 1}, 2 (w & 1) + {0, 1}) of the block.
 __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, const float *Gw, long long TK, int Mpad,
                                                              const float *zs, float c20, float c21, int nsplit,
                                                              double *ppart) {
-    __shared__ double red[kWaves][5];
+    __shared__ double red[kWaves][4];
     const int pair = blockIdx.x, split = blockIdx.y, o = blockIdx.z;
     const int npairs = gridDim.x;
     const int nb = (Mpad + 127) / 128;
@@ -614,7 +624,7 @@ __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, con
     const float c2 = o ? c21 : c20;
     const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
     const float weight = bi == bj ? 1.0f : 2.0f;
-    double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double cacc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -628,29 +638,29 @@ __global__ __launch_bounds__(kThreads) void grad_syrk_kernel(const float *R, con
             }
         }
 #pragma unroll
-    for (int t = 0; t < 5; ++t) {
+    for (int t = 0; t < 4; ++t) {
         const double v = wave_sum(cacc[t]);
         if (lane == 0) red[w][t] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 5) {
+    if (threadIdx.x < 4) {
         const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        ppart[((size_t)(o * npairs + pair) * nsplit + split) * 5 + threadIdx.x] = v;
+        ppart[((size_t)(o * npairs + pair) * nsplit + split) * 4 + threadIdx.x] = v;
     }
 }
 
-// b = sum over workgroups of the partial b, then sum_ij b_i alpha_j dA_ij/dtheta:
-// one thread per row i; bterm[(o * gridDim.x + block) * 5 + theta].
+// b = sum over workgroups of the partial b, then sum_ij b_i alpha_j dA_ij/dlog ell_d:
+// one thread per row i; bterm[(o * gridDim.x + block) * 4 + d].
 __global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const double *bpart, int nwg, int Mpad, const float *zs,
                                                               const float *alpha, float c20, float c21,
                                                               double *bterm) {
-    __shared__ double red[kWaves][5];
+    __shared__ double red[kWaves][4];
     const int o = blockIdx.y;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const float c2 = o ? c21 : c20;
     const float4 *z = reinterpret_cast<const float4 *>(zs) + (size_t)o * Mpad;
     const float *al = alpha + (size_t)o * Mpad;
-    double cacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double cacc[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < Mpad) {
         double b = 0.0;
         for (int wg = 0; wg < nwg; ++wg) b += bpart[((size_t)wg * 2 + o) * Mpad + i];
@@ -660,19 +670,20 @@ __global__ __launch_bounds__(kThreads) void grad_bterm_kernel(const double *bpar
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int t = 0; t < 5; ++t) {
+    for (int t = 0; t < 4; ++t) {
         const double v = wave_sum(cacc[t]);
         if (lane == 0) red[w][t] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 5) {
+    if (threadIdx.x < 4) {
         const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        bterm[((size_t)o * gridDim.x + blockIdx.x) * 5 + threadIdx.x] = v;
+        bterm[((size_t)o * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = v;
     }
 }
 
 // Fixed-order final sums: J = mean smoothed cost, dU[k][c], and the
-// hyperparameter gradient = direct (through k) + (P - b alpha^T) : dA/dtheta.
+// hyperparameter gradient: log ell_d = direct (through k) + (P - b alpha^T) : dA/dlog ell_d;
+// log sf = its folded per-sample terms.
 __global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs, int K, int T, int nwg,
                                                               const float *upart, const double *hpart,
                                                               const double *ppart, int nppart, const double *bterm,
@@ -698,8 +709,10 @@ __global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs
         const int o = tid / 5, t = tid % 5;
         double direct = 0.0, mat = 0.0, bt = 0.0;
         for (int wg = 0; wg < nwg; ++wg) direct += hpart[(size_t)wg * 10 + tid];
-        for (int i = 0; i < nppart; ++i) mat += ppart[((size_t)o * nppart + i) * 5 + t];
-        for (int i = 0; i < nbterm; ++i) bt += bterm[((size_t)o * nbterm + i) * 5 + t];
+        if (t < 4) {
+            for (int i = 0; i < nppart; ++i) mat += ppart[((size_t)o * nppart + i) * 4 + t];
+            for (int i = 0; i < nbterm; ++i) bt += bterm[((size_t)o * nbterm + i) * 4 + t];
+        }
         const float g = (float)(direct + mat - bt);
         if (t < 4) dlog_ell[o * 4 + t] = g;
         else dlog_sf[o] = g;

@@ -78,6 +78,7 @@ struct RolloutArgs {
     unsigned long long *xrec;
     uint32_t *xep;
     int xspin;                      // polls per exchange wait before it gives up; < 0: give up at once
+    uint32_t *flags;                // context status word: GPMPPI_FLAG_EXCHANGE_TIMEOUT is set here
 };
 
 struct UpdateArgs {

@@ -397,7 +397,8 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 // bitwise those of the unsplit kernel.  Both workgroups of a block must be
 // resident together (the launcher checks that the whole grid fits at once);
 // every wait is bounded (RolloutArgs::xspin polls), and a wait that times out
-// yields NaN, which surfaces as non-finite costs.
+// yields NaN, which surfaces as non-finite costs, and sets the exchange
+// time-out bit of the context's status word.
 
 __device__ __forceinline__ uint32_t xch_tag(uint32_t epoch, int k) {
     return ((epoch & 0x7FFFFu) << 13) | (uint32_t)(k + 1);   // k + 1 <= 4096 < 2^13
@@ -588,6 +589,9 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         }
         if (writer) a.costs[sg] = S_;
     }
+    // a wave whose exchange wait gave up reports it in the status word
+    if (broken && lane == 0 && a.flags)
+        __hip_atomic_fetch_or(a.flags, GPMPPI_FLAG_EXCHANGE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the last workgroup to finish advances the epoch for the next launch
     __syncthreads();
     if (tid == 0) {

@@ -39,6 +39,50 @@ gpmppi_status fail(gpmppi_status st, const char *fmt, ...) {
 
 bool is_fin(double x) { return std::isfinite(x); }
 
+// Captures one closed-loop step (enqueue, given the capture stream) into a HIP
+// graph on a private stream that first waits for the work already queued on st,
+// replays it n times, and makes st wait for the replays.  The stream, event,
+// graph and executable it creates are released on every return path.
+template <class Enqueue>
+gpmppi_status replay_captured(hipStream_t st, int n, Enqueue &&enqueue) {
+    struct Owned {
+        hipStream_t cap = nullptr;
+        hipEvent_t ready = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool capturing = false;
+        ~Owned() {
+            if (capturing) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+            }
+            if (cap) (void)hipStreamSynchronize(cap);
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (ready) (void)hipEventDestroy(ready);
+            if (cap) (void)hipStreamDestroy(cap);
+        }
+    } o;
+    HIP_TRY(hipStreamCreateWithFlags(&o.cap, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&o.ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(o.ready, st));
+    HIP_TRY(hipStreamWaitEvent(o.cap, o.ready, 0));
+    HIP_TRY(hipStreamBeginCapture(o.cap, hipStreamCaptureModeThreadLocal));
+    o.capturing = true;
+    const gpmppi_status s = enqueue(o.cap);
+    o.capturing = false;
+    const hipError_t ce = hipStreamEndCapture(o.cap, &o.graph);
+    if (s != GPMPPI_OK) return s;
+    if (ce != hipSuccess) return fail(GPMPPI_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&o.exec, o.graph, nullptr, nullptr, 0));
+    for (int t = 0; t < n; ++t) HIP_TRY(hipGraphLaunch(o.exec, o.cap));
+    HIP_TRY(hipEventRecord(o.ready, o.cap));
+    HIP_TRY(hipStreamWaitEvent(st, o.ready, 0));
+    HIP_TRY(hipStreamSynchronize(o.cap));
+    return GPMPPI_OK;
+}
+
 // Phi^-1(p): the upper-tail probability q = min(p, 1-p) is inverted by
 // bisection on 0.5 erfc(z / sqrt 2) = q over [0, 40], refined by Newton steps.
 double norm_quantile(double p) {
@@ -278,6 +322,7 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     a.xrec = c->xrec;
     a.xep = c->xep;
     a.xspin = c->xspin;
+    a.flags = c->flags;
     a.x0 = x0;
     a.U = U;
     a.costs = costs;
@@ -634,29 +679,7 @@ gpmppi_status gpmppi_closed_loop(gpmppi_ctx *c, float *x_d, float *U_d, uint64_t
         }
         return GPMPPI_OK;
     }
-    hipStream_t cap;
-    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipEvent_t ready;
-    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(ready, st));
-    HIP_TRY(hipStreamWaitEvent(cap, ready, 0));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    gpmppi_status s = enqueue(cap);
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
-    if (s != GPMPPI_OK) return s;
-    if (ce != hipSuccess) return fail(GPMPPI_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    for (int t = 0; t < n; ++t) HIP_TRY(hipGraphLaunch(exec, cap));
-    HIP_TRY(hipEventRecord(ready, cap));
-    HIP_TRY(hipStreamWaitEvent(st, ready, 0));
-    HIP_TRY(hipStreamSynchronize(cap));
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    (void)hipEventDestroy(ready);
-    (void)hipStreamDestroy(cap);
-    return GPMPPI_OK;
+    return replay_captured(st, n, enqueue);
 }
 
 gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uint32_t *out_d, void *stream) {
@@ -1081,29 +1104,7 @@ gpmppi_status gpmppi_batch_closed_loop(gpmppi_batch *b, float *x_d, float *U_d, 
         }
         return GPMPPI_OK;
     }
-    hipStream_t cap;
-    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipEvent_t ready;
-    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(ready, st));
-    HIP_TRY(hipStreamWaitEvent(cap, ready, 0));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    gpmppi_status r = enqueue(cap);
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
-    if (r != GPMPPI_OK) return r;
-    if (ce != hipSuccess) return fail(GPMPPI_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    for (int t = 0; t < n_steps; ++t) HIP_TRY(hipGraphLaunch(exec, cap));
-    HIP_TRY(hipEventRecord(ready, cap));
-    HIP_TRY(hipStreamWaitEvent(st, ready, 0));
-    HIP_TRY(hipStreamSynchronize(cap));
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    (void)hipEventDestroy(ready);
-    (void)hipStreamDestroy(cap);
-    return GPMPPI_OK;
+    return replay_captured(st, n_steps, enqueue);
 }
 
 void gpmppi_batch_destroy(gpmppi_batch *b) { delete b; }
@@ -1113,10 +1114,23 @@ double gpmppi_norm_quantile(double p) {
     return norm_quantile(p);
 }
 
-gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, double tau,
-                          int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
-                          float *costs_d, void *stream) {
-    g_last_error.clear();
+// ------------------------------------------------------------------ differentiation form
+}  // extern "C"
+
+namespace {
+
+// Pieces of the gradient's workspace (256-byte aligned offsets) for one call shape.
+struct GradLayout {
+    GradLaunch l{};
+    int C = 1, nck = 1;
+    size_t o_ck = 0, o_seg = 0, o_R = 0, o_G = 0, o_b = 0, o_h = 0, o_u = 0, o_p = 0, o_bt = 0, o_c = 0;
+    size_t bytes = 0;
+};
+
+// Validates a gradient call on the host and lays out its workspace.
+gpmppi_status grad_check(const gpmppi_ctx *c, const float *x0_d, const float *U_d, double tau, int32_t checkpoint_every,
+                         const float *J_d, const float *dU_d, const float *dlog_ell_d, const float *dlog_sf_d,
+                         GradLayout &g) {
     if (!c || !x0_d || !U_d || !J_d || !dU_d || !dlog_ell_d || !dlog_sf_d) return fail(GPMPPI_E_INVALID, "NULL argument");
     if (!is_fin(tau) || !(tau > 0.0)) return fail(GPMPPI_E_INVALID, "tau must be finite and > 0");
     const int K = c->params.K, T = c->params.T, Mpad = c->Mpad;
@@ -1128,38 +1142,41 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     if (c->n_terr > 0) return fail(GPMPPI_E_UNSUPPORTED, "the differentiation form has no terrain ensemble");
     if (c->params.tighten != 0 || c->params.w_goal != 0.0 || c->params.w_term != 0.0)
         return fail(GPMPPI_E_UNSUPPORTED, "the differentiation form has no goal terms or Step-2 tightening");
-    const int C = checkpoint_every;
-    GradLaunch l{};
+    g.C = checkpoint_every;
+    GradLaunch &l = g.l;
     l.nwg = (K + 31) / 32;
-    const int nck = (T + C - 1) / C;
+    g.nck = (T + g.C - 1) / g.C;
     const int nb = (Mpad + 127) / 128;
     l.npairs = nb * (nb + 1) / 2;
     const long long TK = (long long)T * K;
     l.nsplit = (int)std::max(1LL, std::min<long long>({64LL, (512 + 2 * l.npairs - 1) / (2 * l.npairs), (TK + 1) / 2}));
     l.nbterm = (Mpad + kThreads - 1) / kThreads;
-    // workspace layout (256-byte aligned pieces)
     size_t off = 0;
     auto take = [&](size_t nfloat) {
         const size_t at = off;
         off += (nfloat * sizeof(float) + 255) / 256 * 256;
         return at;
     };
-    const size_t o_ck = take((size_t)nck * 20 * K), o_seg = take((size_t)l.nwg * (C + 1) * 28 * 32),
-                 o_R = take((size_t)2 * TK * Mpad), o_G = take((size_t)2 * TK), o_b = take((size_t)l.nwg * 2 * Mpad * 2),
-                 o_h = take((size_t)l.nwg * 10 * 2), o_u = take((size_t)l.nwg * T * 2),
-                 o_p = take((size_t)2 * l.npairs * l.nsplit * 5 * 2), o_bt = take((size_t)2 * l.nbterm * 5 * 2),
-                 o_c = take((size_t)K);
-    if (off > c->grad_ws_bytes) {
-        if (c->grad_ws) (void)hipFree(c->grad_ws);
-        c->grad_ws = nullptr;
-        c->grad_ws_bytes = 0;
-        if (hipMalloc(&c->grad_ws, off) != hipSuccess) {
-            c->grad_ws = nullptr;
-            return fail(GPMPPI_E_NOMEM, "hipMalloc of the %zu-byte gradient workspace failed", off);
-        }
-        c->grad_ws_bytes = off;
-    }
-    char *ws = static_cast<char *>(c->grad_ws);
+    g.o_ck = take((size_t)g.nck * 20 * K);
+    g.o_seg = take((size_t)l.nwg * (g.C + 1) * 28 * 32);
+    g.o_R = take((size_t)2 * TK * Mpad);
+    g.o_G = take((size_t)2 * TK);
+    g.o_b = take((size_t)l.nwg * 2 * Mpad * 2);
+    g.o_h = take((size_t)l.nwg * 10 * 2);
+    g.o_u = take((size_t)l.nwg * T * 2);
+    g.o_p = take((size_t)2 * l.npairs * l.nsplit * 4 * 2);
+    g.o_bt = take((size_t)2 * l.nbterm * 4 * 2);
+    g.o_c = take((size_t)K);
+    g.bytes = off;
+    return GPMPPI_OK;
+}
+
+// Enqueues the adjoint rollout and its reductions with the workspace at ws (device memory of at
+// least g.bytes; no part of it needs to start at zero).
+gpmppi_status grad_enqueue(const gpmppi_ctx *c, const GradLayout &g, char *ws, const float *x0_d, const float *U_d,
+                           uint64_t seed, double tau, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
+                           float *costs_d, hipStream_t stream) {
+    GradLaunch l = g.l;
     GradArgs a{};
     a.gp = c->gp;
     a.geo = c->geo;
@@ -1168,32 +1185,57 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     a.noise = noise_of(c);
     a.noise.key0 = (uint32_t)seed;
     a.noise.key1 = (uint32_t)(seed >> 32);
-    a.K = K;
-    a.T = T;
-    a.C = C;
-    a.nck = nck;
+    a.K = c->params.K;
+    a.T = c->params.T;
+    a.C = g.C;
+    a.nck = g.nck;
     a.inv_tau = (float)(1.0 / tau);
-    a.inv_K = 1.0f / (float)K;
+    a.inv_K = 1.0f / (float)a.K;
     a.q32 = c->q32;
     a.q_stride = c->q_stride;
     a.x0 = x0_d;
     a.U = U_d;
-    a.costs = costs_d ? costs_d : reinterpret_cast<float *>(ws + o_c);
-    a.ckpt = reinterpret_cast<float *>(ws + o_ck);
-    a.seg = reinterpret_cast<float *>(ws + o_seg);
-    a.R = reinterpret_cast<float *>(ws + o_R);
-    a.Gw = reinterpret_cast<float *>(ws + o_G);
-    a.bpart = reinterpret_cast<double *>(ws + o_b);
-    a.hpart = reinterpret_cast<double *>(ws + o_h);
-    a.upart = reinterpret_cast<float *>(ws + o_u);
-    l.ppart = reinterpret_cast<double *>(ws + o_p);
-    l.bterm = reinterpret_cast<double *>(ws + o_bt);
+    a.costs = costs_d ? costs_d : reinterpret_cast<float *>(ws + g.o_c);
+    a.ckpt = reinterpret_cast<float *>(ws + g.o_ck);
+    a.seg = reinterpret_cast<float *>(ws + g.o_seg);
+    a.R = reinterpret_cast<float *>(ws + g.o_R);
+    a.Gw = reinterpret_cast<float *>(ws + g.o_G);
+    a.bpart = reinterpret_cast<double *>(ws + g.o_b);
+    a.hpart = reinterpret_cast<double *>(ws + g.o_h);
+    a.upart = reinterpret_cast<float *>(ws + g.o_u);
+    l.ppart = reinterpret_cast<double *>(ws + g.o_p);
+    l.bterm = reinterpret_cast<double *>(ws + g.o_bt);
     l.J = J_d;
     l.dU = dU_d;
     l.dlog_ell = dlog_ell_d;
     l.dlog_sf = dlog_sf_d;
-    HIP_TRY(launch_grad(a, l, (hipStream_t)stream));
+    HIP_TRY(launch_grad(a, l, stream));
     return GPMPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, double tau,
+                          int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
+                          float *costs_d, void *stream) {
+    g_last_error.clear();
+    GradLayout g;
+    gpmppi_status st = grad_check(c, x0_d, U_d, tau, checkpoint_every, J_d, dU_d, dlog_ell_d, dlog_sf_d, g);
+    if (st != GPMPPI_OK) return st;
+    if (g.bytes > c->grad_ws_bytes) {
+        if (c->grad_ws) (void)hipFree(c->grad_ws);
+        c->grad_ws = nullptr;
+        c->grad_ws_bytes = 0;
+        if (hipMalloc(&c->grad_ws, g.bytes) != hipSuccess) {
+            c->grad_ws = nullptr;
+            return fail(GPMPPI_E_NOMEM, "hipMalloc of the %zu-byte gradient workspace failed", g.bytes);
+        }
+        c->grad_ws_bytes = g.bytes;
+    }
+    return grad_enqueue(c, g, static_cast<char *>(c->grad_ws), x0_d, U_d, seed, tau, J_d, dU_d, dlog_ell_d,
+                        dlog_sf_d, costs_d, (hipStream_t)stream);
 }
 
 void gpmppi_destroy(gpmppi_ctx *c) { delete c; }

@@ -83,7 +83,7 @@ __device__ __forceinline__ void update_step(const UpdateArgs &a, int k, float *s
     if (k == 0) {
         if (a.weights)
             for (int s = tid; s < a.K; s += kUpdThreads) a.weights[s] = expf((mn - a.costs[s]) * inv_lam) * iz;
-        if (bad && a.flags) atomicOr(a.flags, 1u);
+        if (bad && a.flags) atomicOr(a.flags, GPMPPI_FLAG_NONFINITE);
     }
 }
 

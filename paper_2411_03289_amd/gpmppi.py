@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(HERE, "libgpmppi.so")
 FP32, BF16, BF16X3 = 0, 1, 2
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOT_PD", -3: "E_HIP", -4: "E_NOMEM", -5: "E_NONFINITE",
           -6: "E_UNSUPPORTED"}
+# status bits read by gpmppi_status_flags (GPMPPI_FLAG_* in gpmppi.h)
+FLAG_NONFINITE = 1
+FLAG_EXCHANGE_TIMEOUT = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)

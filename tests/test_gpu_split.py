@@ -143,7 +143,7 @@ def test_split_exchange_timeout_yields_nan_and_the_next_launch_is_exact():
     B.gpmppi_set_exchange_spin(ctx, -1)
     _, S_b, _ = gpu_step(pr, ctx=ctx)
     assert np.all(np.isnan(S_b))
-    assert B.gpmppi_status_flags(ctx) & 1
+    assert B.gpmppi_status_flags(ctx) == B.FLAG_NONFINITE | B.FLAG_EXCHANGE_TIMEOUT
     B.gpmppi_set_exchange_spin(ctx, 0)
     U_c, S_c, w_c = gpu_step(pr, ctx=ctx)
     np.testing.assert_array_equal(S_c, S_a)
