@@ -10,6 +10,19 @@ T=100, M=1024, 50 obstacles, figure-eight track) from its own start state,
 nominal controls and seed: U_new [T,2], costs S [K], weights w [K], and the
 per-sample indicator flip budget at margin band 1e-4 m [K].
 
+    python tests/golden/make_golden.py c1
+
+Output (c1_loop.npz): the receding-horizon loop of Alg. 1 on workload 1
+(K=4096, T=50, M=256, 20 obstacles, figure-eight track) for 100 control
+steps from its start state and zero controls: per step t the state x_t [5]
+the iteration starts from, the warm-started controls U_t [T,2] it is given,
+its result U'_t [T,2] (Philox key seed + t), and the number of samples with
+an indicator margin within 1e-4 m of its threshold; then the plant step with
+U'_t[0] (amplitude 0.3) and the shift.  For the steps that have such samples
+(flagged_steps) it also keeps max S and, for every sample whose weight could
+exceed exp(-40) once its near-threshold indicators flip, (step, sample id,
+S, flip budget) as flagged_rows [n, 4].
+
     python tests/golden/make_golden.py c4
 
 Output (c4_grad.npz): the differentiation form on workload 4 (K=4096, T=50,
@@ -54,6 +67,37 @@ def golden_c2():
                         flip_band=FLIP_BAND)
 
 
+def golden_c1(n_steps=100, amplitude=0.3):
+    from oracle import dynamics as D
+    pr = W.make_config(1)
+    p = pr.params
+    gps = G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)
+    x, U = pr.x0.copy(), pr.U0.copy()
+    xs, U_in, U_out, n_flag = [], [], [], []
+    flagged_steps, S_max, rows = [], [], []
+    t0 = time.time()
+    for t in range(n_steps):
+        xs.append(x.copy())
+        U_in.append(U.copy())
+        U_new, S, w, tr = mppi.iteration(pr, x, U, pr.seed_at(t), gps=gps)
+        flip = mppi.flip_budget(pr, tr, FLIP_BAND)
+        n_flag.append(int((flip > 0).sum()))
+        if n_flag[-1]:
+            flagged_steps.append(t)
+            S_max.append(S.max())
+            keep = np.nonzero((S - flip - S.min()) / p["lam"] <= 40.0)[0]
+            rows.extend([(t, i, S[i], flip[i]) for i in keep])
+        U_out.append(U_new)
+        x = D.plant_step(x, U_new[0], p["dt"], p["tau_v"], p["tau_w"], amplitude)[0]
+        U = mppi.shift(U_new)
+        print(f"step {t + 1}/{n_steps}  flagged {n_flag[-1]}  {time.time() - t0:.0f}s", flush=True)
+    xs.append(x.copy())
+    np.savez_compressed(os.path.join(HERE, "c1_loop.npz"), x=np.array(xs), U_in=np.array(U_in),
+                        U_out=np.array(U_out), n_flag=np.array(n_flag), flagged_steps=np.array(flagged_steps, int),
+                        S_max=np.array(S_max), flagged_rows=np.array(rows, dtype=np.float64).reshape(-1, 4),
+                        amplitude=amplitude, flip_band=FLIP_BAND)
+
+
 def golden_c4(tau=0.05, chunk=512):
     import torch
 
@@ -78,6 +122,8 @@ def golden_c4(tau=0.05, chunk=512):
 
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
+    if "c1" in which:
+        golden_c1()
     if "c2" in which:
         golden_c2()
     if "c4" in which:

@@ -138,3 +138,90 @@ def test_batch_tuning_rejects_inadmissible_shapes():
                 (1, 1, 1, 0, 6)):
         with pytest.raises(B.GpmppiError):
             B.gpmppi_batch_set_tuning(b, *bad)
+
+
+# ------------------------------------------------------------------ the batched workload's own shapes
+C3_SUBSET = (16, 20, 6, 14, 2, 1)   # M 1024, 1024, 512, 512, 64, 256; K up to 16384; both tracks
+
+
+def _c3_subset():
+    return [W.make_batch_problem(pid) for pid in C3_SUBSET]
+
+
+def test_batch_at_workload_shapes_equals_unbatched_runs_at_the_tuned_shape():
+    """Problems of the batched workload with M = 1024 and 512 (LDS plan of M = 1024, the pair walk
+    over W) and K up to 16384, next to M = 64 and 256 (row walk): at the tuner's shape every
+    problem's costs, weights and U equal its own single-problem run at that shape bit for bit."""
+    t = torch()
+    ps = _c3_subset()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    U_off, K_off = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    seed = ps[0].seed + 5
+    chosen = B.gpmppi_batch_tune(b, dev(x0), dev(U), seed, reps=1)
+    print("c3 subset tuning", chosen, flush=True)
+    Uo = t.empty(U_off[-1], device="cuda")
+    costs = t.full((K_off[-1],), float("nan"), device="cuda")
+    w = t.empty(K_off[-1], device="cuda")
+    B.gpmppi_batch_step(b, dev(x0), dev(U), seed, Uo, costs, w)
+    t.cuda.synchronize()
+    Uo, costs, w = Uo.cpu().numpy(), costs.cpu().numpy(), w.cpu().numpy()
+    assert np.all(np.isfinite(costs))
+    for i, p in enumerate(ps):
+        ctx = B.gpmppi_init(p, B.FP32)
+        B.gpmppi_set_tuning(ctx, chosen["groups"], chosen["rotate"], chosen["waves"])
+        U1, S1, w1 = gpu_step(p, B.FP32, seed=seed, ctx=ctx)
+        print(f"problem {p.pid}: K={p.K} T={p.T} M={p.M} n_obs={p.obstacles.shape[0]}", flush=True)
+        np.testing.assert_array_equal(costs[K_off[i]:K_off[i + 1]].astype(np.float64), S1)
+        np.testing.assert_array_equal(Uo[U_off[i]:U_off[i + 1]].reshape(-1, 2).astype(np.float64), U1)
+        np.testing.assert_array_equal(w[K_off[i]:K_off[i + 1]].astype(np.float64), w1)
+
+
+def test_batch_at_workload_shapes_matches_oracle_on_sampled_samples():
+    """Sampled samples of every problem against the oracle's rollout (costs within 1e-5 relative plus
+    the flipped indicators' weights), and each problem's U against the oracle's weights of the
+    batch's own costs and the oracle's sampled controls (Alg. 1's update, 1e-5 relative)."""
+    t = torch()
+    from oracle.philox import sampled_controls
+    ps = _c3_subset()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    U_off, K_off = B.gpmppi_batch_layout(b)
+    x0, U = _pack(ps)
+    seed = ps[0].seed + 6
+    Uo = t.empty(U_off[-1], device="cuda")
+    costs = t.empty(K_off[-1], device="cuda")
+    B.gpmppi_batch_step(b, dev(x0), dev(U), seed, Uo, costs)
+    t.cuda.synchronize()
+    Uo, costs = Uo.cpu().numpy().astype(np.float64), costs.cpu().numpy().astype(np.float64)
+    for i, p in enumerate(ps):
+        S_g = costs[K_off[i]:K_off[i + 1]]
+        ids = np.unique(np.array([0, 31, 32, p.K // 2, p.K - 33, p.K - 1]))
+        S_o, tr_o = mppi.rollout(p, p.x0, p.U0, seed, sample_ids=ids)
+        flip = mppi.flip_budget(p, tr_o, 1e-4)
+        eS = (np.abs(S_g[ids] - S_o) - flip) / np.maximum(S_o, 1.0)
+        q = p.params
+        u_o = sampled_controls(p.U0, np.arange(p.K), seed, (q["sig_v"], q["sig_w"]), q["u_min"], q["u_max"], p.pid)
+        U_ref = mppi.update(mppi.weights(S_g, q["lam"]), u_o)
+        U_g = Uo[U_off[i]:U_off[i + 1]].reshape(-1, 2)
+        eU = np.abs(U_g - U_ref) / np.maximum(np.abs(U_ref), 1.0)
+        print(f"problem {p.pid}: K={p.K} T={p.T} M={p.M} cost err {eS.max():.2e} U err {eU.max():.2e}", flush=True)
+        assert np.all(eS <= 1e-5)
+        assert np.all(eU <= 1e-5)
+
+
+def test_batch_at_workload_shapes_closed_loop_graph_equals_eager():
+    t = torch()
+    ps = _c3_subset()
+    b = B.gpmppi_batch_init(ps, B.FP32)
+    x0, U = _pack(ps)
+    n = 3
+    runs = []
+    for use_graph in (False, True):
+        xd, Ud = dev(x0), dev(U)
+        xh = t.empty((n + 1) * len(ps) * 5, device="cuda")
+        B.gpmppi_batch_closed_loop(b, xd, Ud, ps[0].seed, n, 0.3, xh, use_graph=use_graph)
+        t.cuda.synchronize()
+        runs.append((xh.cpu().numpy(), Ud.cpu().numpy()))
+    for a, c in zip(*runs):
+        assert np.all(np.isfinite(a))
+        np.testing.assert_array_equal(a, c)

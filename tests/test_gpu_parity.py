@@ -1,15 +1,23 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Tolerances (FP32 form), with floors s_q = 1 for positions, heading,
-velocities, costs and controls:
+Bars (FP32 form), with floors s_q = 1 for positions, heading, velocities,
+costs and controls:
   states, costs, U        |g - o| <= 1e-5 max(|o|, s_q)
   cost of a sample whose indicator margin comes within 1e-4 m of its
   threshold                 additionally the weights of those indicators
-  U                       additionally the first-order effect of the cost
-                          tolerance on the weights, (2 tol_S / lambda) sum_s w_s |u_s - U|
+  U                       against sum_s w_s(S_gpu) u_s, the oracle's weights
+                          recomputed from the GPU's own costs (the indicator
+                          decisions are then the same on both sides), and
+                          against the oracle's U where no sample has a margin
+                          within 1e-4 m of its threshold
   GP mean                 1e-5 + 8 eps32 sum_j |k_j alpha_j|   (FP32 dot product)
-  GP variance             2e-6 + 1e-5 s2                     (FP32 W-form, see DESIGN)
+  GP variance             2e-6 + 1e-5 s2                     (FP32 W-form)
+  Sigma_XY, margins       the FP32 forward error bounds of Eq. (10)'s recurrence
+                          and of Eqs. (13)-(16) given the measured state and
+                          variance differences (tests/fp32_bounds.py)
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -19,6 +27,7 @@ from oracle import philox as OP
 from paper_2411_03289_amd import gpmppi as B
 from paper_2411_03289_amd import workloads as W
 
+import fp32_bounds as FB
 from gpu_util import dev, gpu_rollout, gpu_step, rel_err, torch
 
 pytestmark = pytest.mark.gpu
@@ -117,11 +126,19 @@ def test_gp_predict_bf16_forms_ragged(M):
 
 
 def _bf16_bounds(pr, tr_o):
-    """FP32 dot-product bound of each step's GP mean: sum_j |k_j alpha_j| at the oracle's inputs."""
+    """FP32 dot-product bound of each step's GP mean: sum_j |k_j alpha_j| at the oracle's inputs
+    (with a terrain ensemble, alpha = sum_i w_i alpha_i, Eq. 3)."""
     q = np.concatenate([tr_o.x[:-1, :, 3:5], tr_o.u], axis=2).reshape(-1, 4)
-    absdot = np.stack([np.abs(G.se_ard(q, g.Z, g.log_ell, g.log_sf)) @ np.abs(g.alpha)
-                       for g in G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)], axis=1)
-    return absdot.reshape(pr.T, pr.K, 2)
+    if getattr(pr, "terrain_y", None) is not None:
+        tg = G.build_terrains(pr.Z, pr.terrain_y, pr.log_ell, pr.log_sf, pr.log_sn)
+        alphas = [sum(w * tg[i][o].alpha for i, w in enumerate(pr.terrain_w)) for o in range(2)]
+        gps = tg[0]
+    else:
+        gps = G.build_pair(pr.Z, pr.y, pr.log_ell, pr.log_sf, pr.log_sn)
+        alphas = [g.alpha for g in gps]
+    absdot = np.stack([np.abs(G.se_ard(q, g.Z, g.log_ell, g.log_sf)) @ np.abs(a)
+                       for g, a in zip(gps, alphas)], axis=1)
+    return absdot.reshape(tr_o.u.shape[0], tr_o.u.shape[1], 2)
 
 
 def _check_bf16_rollout(prec, S_g, tr_g, tr_o, absdot, label):
@@ -194,30 +211,73 @@ def test_not_positive_definite_is_reported():
 
 
 # ------------------------------------------------------------------ rollout parity
-def _check_rollout(pr, S_g, tr_g, S_o, tr_o, label):
-    T, K = pr.T, pr.K
+def _mean_bound(pr, tr_o):
+    """FP32 dot-product bound of each step's GP mean [T, K, 2]: 1e-5 + 8 eps32 sum_j |k_j alpha_j|
+    at the oracle's queries (Eq. 3's mean)."""
+    return 1e-5 + 8 * EPS32 * _bf16_bounds(pr, tr_o)
+
+
+def _nominal_traces(pr, ctx):
+    """Alg. 1 Step 2's nominal sequence: the oracle's and the GPU's one-sample zero-noise rollout,
+    the GPU's at the launch shape of ctx (its tightening table is that rollout's covariance)."""
+    pn = dataclasses.replace(pr, K=1, params=dict(pr.params, sig_v=0.0, sig_w=0.0, tighten=0))
+    _, tr_n = mppi.rollout(pn, pr.x0, pr.U0, 0)
+    cn = B.gpmppi_init(pn, B.FP32)
+    tun = B.gpmppi_get_tuning(ctx)
+    B.gpmppi_set_tuning(cn, tun["groups"], tun["rotate"], tun["waves"], tun["split"])
+    _, tg = gpu_rollout(pn, ctx=cn, seed=0)
+    return tr_n, tg["x"], tg["gp_var"]
+
+
+def _margin_covariance(pr, tr_o, E, nominal):
+    """Position covariance [T, K, 3] each step's margins use (at k + 1) and its bound: the sample's
+    own (R7), or with Step-2 tightening the nominal sequence's (R27)."""
+    if pr.params.get("tighten", 0) != 1:
+        return tr_o.sxy[1:], FB.position_block(E)[1:]
+    assert nominal is not None, "Step-2 tightening needs the nominal traces"
+    tr_n, x_n, var_n = nominal
+    En, _ = FB.sigma_bound(pr, tr_n.x, tr_n.gp_var, x_n, var_n)
+    K = tr_o.x.shape[1]
+    return (np.repeat(tr_n.sxy[1:, :1], K, axis=1), np.repeat(FB.position_block(En)[1:, :1], K, axis=1))
+
+
+def _check_rollout(pr, S_g, tr_g, S_o, tr_o, label, nominal=None, mean_bound=None):
     ex = rel_err(tr_g["x"], tr_o.x, 1.0)
     eu = np.abs(tr_g["u"] - tr_o.u)
     em = np.abs(tr_g["gp_mean"] - tr_o.gp_mean)
     ev = np.abs(tr_g["gp_var"] - tr_o.gp_var)
-    pos = np.maximum(np.abs(tr_o.x[1:, :, 0]), np.abs(tr_o.x[1:, :, 1]))
-    edl = np.abs(tr_g["d_lane"] - tr_o.d_lane) / np.maximum(pos, 1.0)
-    esxy = np.abs(tr_g["sxy"] - tr_o.sxy) / np.maximum(np.abs(tr_o.sxy), 1e-6)
+    E, _ = FB.sigma_bound(pr, tr_o.x, tr_o.gp_var, tr_g["x"], tr_g["gp_var"])
+    exy = FB.position_block(E)
+    sxy_c, exy_c = _margin_covariance(pr, tr_o, E, nominal)
+    esxy = np.abs(tr_g["sxy"] - tr_o.sxy)
+    edl = np.abs(tr_g["d_lane"] - tr_o.d_lane)
+    bdl = FB.lane_distance_bound(pr, tr_o.x, tr_g["x"], tr_o.d_lane)
+    elm = np.abs(tr_g["lane_margin"] - tr_o.lane_margin)
+    blm = FB.lane_margin_bound(pr, tr_o.x, tr_g["x"], tr_o.d_lane, sxy_c, exy_c)
+    fin = np.isfinite(tr_o.obs_margin)
+    eom = np.where(fin, np.abs(np.where(fin, tr_g["obs_margin"], 0.0) - np.where(fin, tr_o.obs_margin, 0.0)), 0.0)
+    bom = FB.obstacle_margin_bound(pr, tr_o.x, tr_g["x"], sxy_c, exy_c)
     flip = mppi.flip_budget(pr, tr_o, FLIP_BAND)
     eS = np.abs(S_g - S_o) - flip
+    mb = _mean_bound(pr, tr_o) if mean_bound is None else mean_bound
+
+    def frac(e, b):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return float(np.max(np.where(b > 0, e / b, np.where(e > 0, np.inf, 0.0))))
+
     _print(label, x=ex.max(), u=eu.max(), gp_mean=em.max(), gp_var=ev.max(), d_lane=edl.max(),
-           sxy_rel=esxy.max(), cost=(eS / np.maximum(S_o, 1)).max(), flagged=float((flip > 0).sum()))
+           sxy_of_bound=frac(esxy, exy), lane_margin=elm.max(), lane_of_bound=frac(elm, blm),
+           obs_margin=eom.max(), obs_of_bound=frac(eom, bom),
+           cost=(eS / np.maximum(S_o, 1)).max(), flagged=float((flip > 0).sum()))
     assert np.all(ex <= TOL), "states"
     assert np.all(eu <= 1e-5), "sampled controls"
+    assert np.all(em <= mb), "gp mean"
     assert np.all(ev <= 2e-6 + 1e-5 * tr_o.gp_var), "gp variance"
-    assert np.all(edl <= 2 * TOL), "lane distance"
-    assert np.all(esxy <= 1e-3), "position covariance"
-    lm_ok = np.abs(tr_g["lane_margin"] - tr_o.lane_margin) <= 2 * TOL * np.maximum(pos, 1.0) + 1e-4
-    assert np.all(lm_ok), "lane margin"
-    fin = np.isfinite(tr_o.obs_margin)
+    assert np.all(edl <= bdl), "lane distance"
+    assert np.all(esxy <= exy), "position covariance"
+    assert np.all(elm <= blm), "lane margin"
     assert np.array_equal(np.isfinite(tr_g["obs_margin"]), fin)
-    om_ok = np.abs(tr_g["obs_margin"][fin] - tr_o.obs_margin[fin]) <= 2 * TOL * np.maximum(pos[fin], 1.0) + 1e-4
-    assert np.all(om_ok), "obstacle margin"
+    assert np.all(eom <= bom), "obstacle margin"
     assert np.all(eS <= TOL * np.maximum(S_o, 1.0)), "costs"
 
 
@@ -242,11 +302,40 @@ def test_rollout_trace_matches_oracle(case):
 
 
 def _u_tolerance(pr, S_o, w_o, u_o, U_o, flip):
+    """Where indicator margins lie within the flip band, the oracle's U may move by the weights of
+    the indicators that flip: first-order effect of the cost tolerance plus the flipped weights."""
     lam = pr.params["lam"]
     tolS = TOL * np.maximum(S_o, 1.0)
     spread = np.einsum("s,tsc->tc", w_o, np.abs(u_o - U_o[:, None, :]))
     infl = np.einsum("s,tsc->tc", w_o * (np.expm1(np.minimum(flip / lam, 50.0))), np.abs(u_o - U_o[:, None, :]))
     return TOL * np.maximum(np.abs(U_o), 1.0) + 2 * tolS.max() / lam * spread + 2 * infl
+
+
+def _check_update(pr, U_g, S_g, w_g, u_o, U_o, S_o, w_o, flip, label):
+    """Alg. 1's weights and weighted update at 1e-5 relative: (1) against the oracle's weights of the
+    GPU's own costs and the oracle's sampled controls, which fixes the indicator decisions to the
+    GPU's; (2) against the oracle's own U wherever no sample has an indicator margin within the
+    flip band (otherwise within the flipped indicators' effect)."""
+    lam = pr.params["lam"]
+    w_ref = mppi.weights(S_g, lam)
+    U_ref = mppi.update(w_ref, u_o)
+    e_ref = np.abs(U_g - U_ref) / np.maximum(np.abs(U_ref), 1.0)
+    e_o = np.abs(U_g - U_o) / np.maximum(np.abs(U_o), 1.0)
+    n_flag = int((flip > 0).sum())
+    vals = dict(U_vs_own_cost_weights=e_ref.max(), U_vs_oracle=e_o.max(), flagged=float(n_flag))
+    if w_g is not None:
+        # FP32 weights: the exponent (S - min S) / lambda carries about 2 eps32 of its size
+        gap = (S_g - S_g.min()) / lam
+        ew = np.abs(w_g - w_ref)
+        vals["w_of_bound"] = float(np.max(ew / ((TOL + 4 * EPS32 * gap) * w_ref + 1e-37)))
+        assert np.all(ew <= (TOL + 4 * EPS32 * gap) * w_ref + 1e-37), "weights of the GPU's costs"
+        assert abs(w_g.sum() - 1.0) <= TOL
+    _print(label, **vals)
+    assert np.all(e_ref <= TOL), "U against the weights of the GPU's costs"
+    if n_flag == 0:
+        assert np.all(e_o <= TOL), "U against the oracle"
+    else:
+        assert np.all(np.abs(U_g - U_o) <= _u_tolerance(pr, S_o, w_o, u_o, U_o, flip)), "U against the oracle"
 
 
 @pytest.mark.parametrize("cfg", ["c0", "small_eight"])
@@ -256,12 +345,8 @@ def test_step_matches_oracle(cfg):
     U_g, S_g, w_g = gpu_step(pr)
     U_o, S_o, w_o, tr_o = mppi.iteration(pr)
     flip = mppi.flip_budget(pr, tr_o, FLIP_BAND)
-    tolU = _u_tolerance(pr, S_o, w_o, tr_o.u, U_o, flip)
-    _print(f"step {cfg}", U=np.abs(U_g - U_o).max(), tolU=tolU.min(), w=np.abs(w_g - w_o).max())
     assert np.all(np.abs(S_g - S_o) <= TOL * np.maximum(S_o, 1) + flip)
-    assert np.all(np.abs(U_g - U_o) <= tolU)
-    assert abs(w_g.sum() - 1.0) < 1e-5
-    assert np.all(np.abs(w_g - w_o) <= 1e-4 * np.maximum(w_o, 1e-3 / pr.K) + 2 * w_o * np.expm1(flip))
+    _check_update(pr, U_g, S_g, w_g, tr_o.u, U_o, S_o, w_o, flip, f"step {cfg}")
 
 
 def test_weights_update_alone():
@@ -289,10 +374,9 @@ def test_c1_single_iteration():
     U_g, S_g, w_g = gpu_step(pr)
     U_o, S_o, w_o, tr_o = mppi.iteration(pr)
     flip = mppi.flip_budget(pr, tr_o, FLIP_BAND)
-    tolU = _u_tolerance(pr, S_o, w_o, tr_o.u, U_o, flip)
-    _print("step c1", U=np.abs(U_g - U_o).max(), cost=(np.abs(S_g - S_o) / np.maximum(S_o, 1)).max())
+    _print("step c1", cost=(np.abs(S_g - S_o) / np.maximum(S_o, 1)).max())
     assert np.all(np.abs(S_g - S_o) <= TOL * np.maximum(S_o, 1) + flip)
-    assert np.all(np.abs(U_g - U_o) <= tolU)
+    _check_update(pr, U_g, S_g, w_g, tr_o.u, U_o, S_o, w_o, flip, "step c1")
 
 
 def test_c2_full_size_sampled_and_golden():
@@ -305,19 +389,85 @@ def test_c2_full_size_sampled_and_golden():
     sub = {k: (v[:, ids] if v.ndim >= 2 else v) for k, v in tr_g.items()}
     prs = W.make_config(2, K=len(ids))
     _check_rollout(prs, S_g[ids], sub, S_o, tr_o, "c2 sampled")
-    if os.path.exists(path):
-        g = np.load(path)
-        U_g, S_full, _ = gpu_step(pr)
-        np.testing.assert_array_equal(S_full, S_g)   # step and rollout agree bitwise
-        assert np.all(np.abs(S_g - g["S"]) <= TOL * np.maximum(g["S"], 1) + g["flip"])
-        tolS = TOL * np.maximum(g["S"], 1.0).max()
-        # sample controls for the U bound come from the oracle's noise
-        from oracle.philox import sampled_controls
-        p = pr.params
-        u_o = sampled_controls(pr.U0, np.arange(pr.K), pr.seed, (p["sig_v"], p["sig_w"]), p["u_min"], p["u_max"])
-        tolU = _u_tolerance(pr, g["S"], g["w"], u_o, g["U"], g["flip"])
-        _print("c2 full", U=np.abs(U_g - g["U"]).max(), tolU=tolU.min(), tolS=tolS)
-        assert np.all(np.abs(U_g - g["U"]) <= tolU)
+    g = np.load(path)
+    U_g, S_full, w_g = gpu_step(pr)
+    np.testing.assert_array_equal(S_full, S_g)   # step and rollout agree bitwise
+    assert np.all(np.abs(S_g - g["S"]) <= TOL * np.maximum(g["S"], 1) + g["flip"])
+    # the update's sampled controls are the oracle's (Philox words are bit-exact, Box-Muller in FP64)
+    from oracle.philox import sampled_controls
+    p = pr.params
+    u_o = sampled_controls(pr.U0, np.arange(pr.K), pr.seed, (p["sig_v"], p["sig_w"]), p["u_min"], p["u_max"])
+    _check_update(pr, U_g, S_g, w_g, u_o, g["U"], g["S"], g["w"], g["flip"], "c2 full")
+
+
+# BF16 forms at c2: the variance bars of the GP-level tests, and the U bars the forms are stated at
+FORM_VAR_TOL = {B.BF16X3: 5e-5, B.BF16: 2e-2}
+FORM_U_TOL = {B.BF16X3: 1e-5, B.BF16: 1e-3}
+
+
+def _form_margin_band(pr, tr_g, vtol):
+    """Per (step, sample) bounds [T, K] on |margin_gpu - margin_oracle| (lane, obstacle) for a form
+    whose GP variances are within vtol of the oracle's and whose states are within the FP32 bar:
+    the forward error bounds of Eq. (10) and Eqs. (13)-(16) evaluated around the GPU's own
+    trajectory (first order in the variance error)."""
+    x_g, var_g = tr_g["x"], tr_g["gp_var"]
+    x_p = x_g + TOL * np.maximum(np.abs(x_g), 1.0)
+    E, sig = FB.sigma_bound(pr, x_g, var_g, x_p, var_g + vtol)
+    sxy, exy = FB.position_block(sig)[1:], FB.position_block(E)[1:]
+    return (FB.lane_margin_bound(pr, x_g, x_p, tr_g["d_lane"], sxy, exy),
+            FB.obstacle_margin_bound(pr, x_g, x_p, sxy, exy))
+
+
+@pytest.mark.parametrize("prec", [B.BF16, B.BF16X3])
+def test_c2_bf16_forms_end_to_end(prec):
+    """The precision forms at c2's full size, end to end.  States, controls and GP means stay at the
+    FP32 bar (the trajectory depends on the means only); on sampled samples each cost is within
+    w_var sum_k |ds2_k| (its measured variance differences) plus the weights of the indicators whose
+    margin lies within the measured margin differences; every cost is within 2 T w_var vtol plus the
+    weights of the indicators whose own margin lies within the band that vtol allows (an indicator
+    can differ from the oracle's only where the margin's sign can); U is within the form's stated
+    bar of the oracle's U."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.npz"))
+    pr = W.make_config(2)
+    vtol, utol = FORM_VAR_TOL[prec], FORM_U_TOL[prec]
+    ctx = B.gpmppi_init(pr, prec)
+    S_g, tr_g = gpu_rollout(pr, ctx=ctx)
+    U_g, S2, _ = gpu_step(pr, ctx=ctx)
+    np.testing.assert_array_equal(S2, S_g)
+    # sampled samples against the oracle's traces
+    ids = np.unique(np.concatenate([np.arange(0, pr.K, 257), [pr.K - 1, pr.K - 32, 31, 32]]))
+    S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed, sample_ids=ids)
+    sub = {k: (v[:, ids] if v.ndim >= 2 else v) for k, v in tr_g.items()}
+    prs = W.make_config(2, K=len(ids))
+    absdot = _bf16_bounds(prs, tr_o)
+    _check_bf16_rollout(prec, S_g[ids], sub, tr_o, absdot, f"c2 form={prec} sampled")
+    dvar = np.abs(sub["gp_var"] - tr_o.gp_var)
+    band = np.maximum(np.abs(sub["lane_margin"] - tr_o.lane_margin),
+                      np.where(np.isfinite(tr_o.obs_margin),
+                               np.abs(np.nan_to_num(sub["obs_margin"] - tr_o.obs_margin, posinf=0.0)), 0.0))
+    p = pr.params
+    disc = p["discount"] ** np.arange(pr.T)
+    near_lane = np.abs(tr_o.lane_margin) <= band + 1e-4
+    near_obs = np.abs(tr_o.obs_margin) <= band + 1e-4
+    flip_s = p["w_lane"] * (near_lane * disc[:, None]).sum(0) + p["w_obs"] * near_obs.sum(0)
+    bound_s = TOL * np.maximum(S_o, 1.0) + p["w_var"] * dvar.sum(axis=(0, 2)) + flip_s
+    eS_s = np.abs(S_g[ids] - S_o)
+    # every sample against the stored oracle costs
+    bl, bo = _form_margin_band(pr, tr_g, vtol)
+    near_lane = np.abs(tr_g["lane_margin"]) <= bl
+    near_obs = np.isfinite(tr_g["obs_margin"]) & (np.abs(tr_g["obs_margin"]) <= bo)
+    flip_all = p["w_lane"] * (near_lane * disc[:, None]).sum(0) + p["w_obs"] * near_obs.sum(0)
+    bound_all = TOL * np.maximum(g["S"], 1.0) + 2 * pr.T * p["w_var"] * vtol + flip_all
+    mb = float(max(bl.max(), bo.max()))
+    eS_all = np.abs(S_g - g["S"])
+    eU = np.abs(U_g - g["U"])
+    _print(f"c2 form={prec}", cost_sampled=eS_s.max(), cost_sampled_of_bound=(eS_s / bound_s).max(),
+           cost_all=eS_all.max(), cost_all_of_bound=(eS_all / bound_all).max(), margin_band_max=mb,
+           flagged=float((flip_all > 0).sum()), U=eU.max())
+    assert np.all(eS_s <= bound_s), "sampled costs"
+    assert np.all(eS_all <= bound_all), "costs"
+    assert np.all(eU <= utol * np.maximum(np.abs(g["U"]), 1.0)), "U"
 
 
 def test_determinism_and_aliasing():
@@ -359,9 +509,10 @@ def test_closed_loop_resynced_steps_and_graph_replay():
     x, U = pr.x0.copy(), pr.U0.copy()
     for step in range(4):
         U_o, S_o, w_o, tr_o = mppi.iteration(pr, x, U, pr.seed_at(step), gps=gps)
-        U_g, S_g, _ = gpu_step(pr, x0=x, U=U, seed=pr.seed_at(step), ctx=ctx)
+        U_g, S_g, w_g = gpu_step(pr, x0=x, U=U, seed=pr.seed_at(step), ctx=ctx)
         flip = mppi.flip_budget(pr, tr_o, FLIP_BAND)
-        assert np.all(np.abs(U_g - U_o) <= _u_tolerance(pr, S_o, w_o, tr_o.u, U_o, flip))
+        assert np.all(np.abs(S_g - S_o) <= TOL * np.maximum(S_o, 1) + flip)
+        _check_update(pr, U_g, S_g, w_g, tr_o.u, U_o, S_o, w_o, flip, f"closed loop step {step}")
         # plant + shift on the device from the oracle's U'
         xd, Ud = dev(x), dev(U_o)
         B.gpmppi_plant_shift(ctx, xd, xd, Ud, 0.3)
@@ -423,10 +574,12 @@ def test_goal_terms_and_step2_tightening(mode):
         pr.params["tighten"] = 1
     else:
         pr.params.update(W.task_params("avoid", goal=(0.3, 0.2) if mode == "goal_reached" else (6.0, -6.0)))
-    S_g, tr_g = gpu_rollout(pr)
+    ctx = B.gpmppi_init(pr, B.FP32)
+    S_g, tr_g = gpu_rollout(pr, ctx=ctx)
     S_o, tr_o = mppi.rollout(pr, pr.x0, pr.U0, pr.seed)
-    _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"rollout {mode}")
-    U_g, S2, _ = gpu_step(pr)
+    nominal = _nominal_traces(pr, ctx) if mode == "step2" else None
+    _check_rollout(pr, S_g, tr_g, S_o, tr_o, f"rollout {mode}", nominal=nominal)
+    U_g, S2, _ = gpu_step(pr, ctx=ctx)
     np.testing.assert_array_equal(S2, S_g)
 
 
