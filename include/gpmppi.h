@@ -234,6 +234,22 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, 
                           int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
                           float *costs_d, void *stream);
 
+/* Allocation-free gpmppi_grad, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, computation and results, with the
+ * workspace taken from a fixed scratch array of GPMPPI_GRAD_SCRATCH_BYTES that
+ * the library keeps on each GPU it runs on until the process ends, instead of
+ * the context's own workspace.  Calls no allocating routine.  A problem whose
+ * workspace exceeds the array (about 8 T K M_pad bytes plus per-sample
+ * checkpoints) fails with GPMPPI_E_NOMEM and enqueues nothing.  Every call on
+ * a GPU shares that GPU's array and leaves its contents behind (no part of it
+ * needs to start at zero): calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. */
+#define GPMPPI_GRAD_SCRATCH_BYTES (128u << 20)
+gpmppi_status gpmppi_grad_noalloc(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, double tau,
+                                  int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d,
+                                  float *dlog_sf_d, float *costs_d, void *stream);
+
 /* ------------------------------------------------------------------ launch shapes
  * The rollout's launch shape, chosen per context (or batch) by measurement.
  * None of these changes what is computed; they change the grouping of the

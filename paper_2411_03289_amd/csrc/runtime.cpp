@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,39 @@ gpmppi_status set_error(gpmppi_status st, const char *msg) { return fail(st, "%s
 
 constexpr int kGradMaxMpad = 512;   // the adjoint's LDS plan holds k and r for 32 samples
 
+// Scratch memory of the allocation-free entry point (gpmppi_grad_noalloc): one
+// array per GPU the library runs on, held until the process ends and shared by
+// every call on that GPU.  Host code never uses this name as an address: each
+// device's address comes from scratch_address() and is kept per device.
+constexpr size_t kScratchBytes = size_t(GPMPPI_GRAD_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+gpmppi_status scratch_address(int dev, void **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return fail(GPMPPI_E_UNSUPPORTED, "device %d is beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GPMPPI_E_HIP, "hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GPMPPI_OK;
+}
+
+}  // namespace
+
 struct gpmppi_ctx {
     int device = 0;
     gpmppi_params params{};
@@ -142,6 +176,7 @@ struct gpmppi_ctx {
     long long q_stride = 0;          // float4 per output
     void *grad_ws = nullptr;         // differentiation-form workspace (grown on demand)
     size_t grad_ws_bytes = 0;
+    void *scratch = nullptr;         // this device's allocation-free scratch array (not owned)
     float4 *obs = nullptr;
     float4 *seg = nullptr;
     float *seg_inv = nullptr;
@@ -381,8 +416,11 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GPMPPI_E_HIP, "no HIP device available");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
+    void *scratch_ptr = nullptr;
+    if ((st = scratch_address(dev, &scratch_ptr)) != GPMPPI_OK) return st;
     auto *c = new gpmppi_ctx();
     c->device = dev;
+    c->scratch = scratch_ptr;
     c->params = *params;
     c->M = gp[0].M;
     c->Mpad = (c->M + 63) / 64 * 64;   // an even number of 32-row tiles (pairs of row tiles)
@@ -1235,6 +1273,23 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
         c->grad_ws_bytes = g.bytes;
     }
     return grad_enqueue(c, g, static_cast<char *>(c->grad_ws), x0_d, U_d, seed, tau, J_d, dU_d, dlog_ell_d,
+                        dlog_sf_d, costs_d, (hipStream_t)stream);
+}
+
+gpmppi_status gpmppi_grad_noalloc(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, double tau,
+                                  int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d,
+                                  float *dlog_sf_d, float *costs_d, void *stream) {
+    g_last_error.clear();
+    GradLayout g;
+    gpmppi_status st = grad_check(c, x0_d, U_d, tau, checkpoint_every, J_d, dU_d, dlog_ell_d, dlog_sf_d, g);
+    if (st != GPMPPI_OK) return st;
+    if (g.bytes > kScratchBytes)
+        return fail(GPMPPI_E_NOMEM,
+                    "the allocation-free gradient needs %zu bytes of scratch, more than its %zu-byte maximum "
+                    "(about 8 T K M_pad bytes are needed; use gpmppi_grad)",
+                    g.bytes, kScratchBytes);
+    if (!c->scratch) return fail(GPMPPI_E_HIP, "the scratch array of this context's device has no address");
+    return grad_enqueue(c, g, static_cast<char *>(c->scratch), x0_d, U_d, seed, tau, J_d, dU_d, dlog_ell_d,
                         dlog_sf_d, costs_d, (hipStream_t)stream);
 }
 

@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_batch_closed_loop": [vp, vp, vp, u64, i32, f64, vp, i32, vp],
         "gpmppi_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
         "gpmppi_grad": [vp, vp, vp, u64, f64, i32, vp, vp, vp, vp, vp, vp],
+        "gpmppi_grad_noalloc": [vp, vp, vp, u64, f64, i32, vp, vp, vp, vp, vp, vp],
         "gpmppi_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_set_exchange_spin": [vp, i32],
         "gpmppi_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
@@ -454,6 +455,19 @@ def gpmppi_grad(ctx: Context, x0, U, seed: int, tau: float, checkpoint_every: in
                              int(checkpoint_every), _dev(J, 1, "J"), _dev(dU, 2 * T, "dU"),
                              _dev(dlog_ell, 8, "dlog_ell"), _dev(dlog_sf, 2, "dlog_sf"),
                              _dev(costs, K, "costs", optional=True), _stream(stream)))
+
+
+GRAD_SCRATCH_BYTES = 128 << 20   # GPMPPI_GRAD_SCRATCH_BYTES
+
+
+def gpmppi_grad_noalloc(ctx: Context, x0, U, seed: int, tau: float, checkpoint_every: int, J, dU, dlog_ell,
+                        dlog_sf, costs=None, stream=None):
+    """gpmppi_grad without any device allocation (the library's per-GPU scratch array)."""
+    K, T = ctx.params["K"], ctx.params["T"]
+    _check(lib().gpmppi_grad_noalloc(ctx.handle, _dev(x0, 5, "x0"), _dev(U, 2 * T, "U"), ctypes.c_uint64(seed),
+                                     float(tau), int(checkpoint_every), _dev(J, 1, "J"), _dev(dU, 2 * T, "dU"),
+                                     _dev(dlog_ell, 8, "dlog_ell"), _dev(dlog_sf, 2, "dlog_sf"),
+                                     _dev(costs, K, "costs", optional=True), _stream(stream)))
 
 
 class GradProblem:
