@@ -108,18 +108,28 @@ def form_errors(B, torch, pr, tr, forms):
     return out
 
 
-def extras(B, W, torch, log_fn):
+EXTRAS = ("c1_closed_loop", "c3_batch", "c3_batch_bf16", "c4_grad")
+
+
+def extras(B, W, torch, log_fn, only=None, steps=None):
     """Informational timings of the other workloads (not the reported value):
     c1 closed loop (K=4096, T=50, M=256, 100 steps, HIP graph), c3 batch (64
     problems of uneven shape, 50 closed-loop steps in one persistent launch per
     step, HIP graph, tuned; FP32, and the same in the BF16 form), c4 gradient
-    (K=4096, T=50, M=512, tau 0.05 m, checkpoints every 10 steps)."""
+    (K=4096, T=50, M=512, tau 0.05 m, checkpoints every 10 steps).  only: run
+    just that one (for profiling); steps: fewer closed-loop steps or gradients."""
     import numpy as np
     out = {}
+    want = lambda name: only is None or only == name   # noqa: E731
     f32 = dict(device="cuda", dtype=torch.float32)
     ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731
     stream = torch.cuda.current_stream()
+    n_c1 = steps or 100
+    n_c3 = steps or 50
+    n_c4 = steps or 3
     try:   # c1 closed loop
+        if not want("c1_closed_loop"):
+            raise LookupError
         pr = W.make_config(1)
         ctx = B.gpmppi_init(pr, B.FP32)
         shape = B.gpmppi_tune(ctx, torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32), pr.seed, 2, stream)
@@ -129,18 +139,22 @@ def extras(B, W, torch, log_fn):
         e0, e1 = ev(), ev()
         torch.cuda.synchronize()
         e0.record(stream)
-        B.gpmppi_closed_loop(ctx, x, U, pr.seed, 100, 0.3, use_graph=True, stream=stream)
+        B.gpmppi_closed_loop(ctx, x, U, pr.seed, n_c1, 0.3, use_graph=True, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 100
+        ms = e0.elapsed_time(e1) / n_c1
         out["c1_closed_loop"] = {"ms_per_control_step": ms, "sample_steps_per_s": pr.K * pr.T / (ms * 1e-3),
-                                 "workload": "K=4096 T=50 M=256 20 obstacles figure-eight, 100 steps, HIP graph",
+                                 "workload": f"K=4096 T=50 M=256 20 obstacles figure-eight, {n_c1} steps, HIP graph",
                                  "shape": {k: shape[k] for k in ("groups", "rotate", "waves", "split")}}
         log_fn(f"[bench] extra c1 closed loop {ms:.3f} ms/step")
         del ctx
+    except LookupError:
+        pass
     except Exception as exc:   # informational only
         out["c1_closed_loop"] = {"error": repr(exc)}
     try:   # c3 batch
+        if not want("c3_batch"):
+            raise LookupError
         probs = [W.make_batch_problem(p) for p in range(64)]
         b = B.gpmppi_batch_init(probs, B.FP32)
         U_off, K_off = B.gpmppi_batch_layout(b)
@@ -153,20 +167,24 @@ def extras(B, W, torch, log_fn):
         e0, e1 = ev(), ev()
         torch.cuda.synchronize()
         e0.record(stream)
-        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 50, 0.3, use_graph=True, stream=stream)
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, n_c3, 0.3, use_graph=True, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 50
+        ms = e0.elapsed_time(e1) / n_c3
         ss = sum(p.K * p.T for p in probs)
         out["c3_batch"] = {"ms_per_control_step": ms, "sample_steps_per_s": ss / (ms * 1e-3),
                            "sample_steps_per_control_step": ss, "shape": shape,
                            "workload": "64 problems, K in {1024..16384}, T in [30, 100], M in {64..1024}, "
-                                       "0-50 obstacles, 50 closed-loop steps, HIP graph"}
+                                       f"0-50 obstacles, {n_c3} closed-loop steps, HIP graph"}
         log_fn(f"[bench] extra c3 batch {ms:.3f} ms/step")
         del b
+    except LookupError:
+        pass
     except Exception as exc:
         out["c3_batch"] = {"error": repr(exc)}
     try:   # c3 batch in the BF16 form (informational: the batching and precision forms together)
+        if not want("c3_batch_bf16"):
+            raise LookupError
         probs = [W.make_batch_problem(p) for p in range(64)]
         b = B.gpmppi_batch_init(probs, B.BF16)
         x0 = torch.tensor(np.concatenate([p.x0 for p in probs]), **f32)
@@ -178,18 +196,22 @@ def extras(B, W, torch, log_fn):
         e0, e1 = ev(), ev()
         torch.cuda.synchronize()
         e0.record(stream)
-        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, 50, 0.3, use_graph=True, stream=stream)
+        B.gpmppi_batch_closed_loop(b, x, U, probs[0].seed, n_c3, 0.3, use_graph=True, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 50
+        ms = e0.elapsed_time(e1) / n_c3
         ss = sum(p.K * p.T for p in probs)
         out["c3_batch_bf16"] = {"ms_per_control_step": ms, "sample_steps_per_s": ss / (ms * 1e-3), "shape": shape,
                                 "workload": "the c3 batch in the BF16 form (informational)"}
         log_fn(f"[bench] extra c3 batch bf16 {ms:.3f} ms/step")
         del b
+    except LookupError:
+        pass
     except Exception as exc:
         out["c3_batch_bf16"] = {"error": repr(exc)}
     try:   # c4 gradient
+        if not want("c4_grad"):
+            raise LookupError
         pr = W.make_config(4)
         ctx = B.gpmppi_init(pr, B.FP32)
         x0, U = torch.tensor(pr.x0, **f32), torch.tensor(pr.U0, **f32)
@@ -199,15 +221,17 @@ def extras(B, W, torch, log_fn):
         e0, e1 = ev(), ev()
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(3):
+        for _ in range(n_c4):
             B.gpmppi_grad(ctx, x0, U, pr.seed, 0.05, 10, J, dU, dle, dls, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 3
+        ms = e0.elapsed_time(e1) / n_c4
         out["c4_grad"] = {"ms_per_gradient": ms, "sample_steps_per_s": pr.K * pr.T / (ms * 1e-3),
                           "workload": "K=4096 T=50 M=512 20 obstacles figure-eight, tau 0.05 m, checkpoints every 10"}
         log_fn(f"[bench] extra c4 gradient {ms:.3f} ms")
         del ctx
+    except LookupError:
+        pass
     except Exception as exc:
         out["c4_grad"] = {"error": repr(exc)}
     return out
@@ -236,6 +260,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
     ap.add_argument("--no-extras", action="store_true", help="skip the informational c1 / c3 / c4 timings")
+    ap.add_argument("--extra", choices=EXTRAS, default=None,
+                    help="run only this informational timing and print it (for profiling; no bench line)")
+    ap.add_argument("--extra-steps", type=int, default=None,
+                    help="closed-loop steps (or gradients) of the informational timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path is single-GPU (multi-GPU sharding is design only); "
@@ -249,6 +277,10 @@ def main():
     from paper_2411_03289_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.extra:
+        print(json.dumps({args.extra: extras(B, W, torch, log, args.extra, args.extra_steps).get(args.extra)}),
+              flush=True)
+        return
     if args.copy_calibrate_mib:
         n = args.copy_calibrate_mib * (1 << 20) // 4
         src = torch.ones(n, device="cuda")
@@ -341,7 +373,7 @@ def main():
                             for n in results if "fp32" in results},
     }
     if not args.no_extras:
-        line["extras"] = extras(B, W, torch, log)
+        line["extras"] = extras(B, W, torch, log, steps=args.extra_steps)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline on {args.cpu_samples} samples")
         line["cpu_baseline"], tr_o = cpu_baseline(pr, args.cpu_samples)

@@ -277,11 +277,14 @@ typedef struct {
 gpmppi_status gpmppi_tune(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
                           gpmppi_tuning *chosen, void *stream);
 /* Output split: the number of polls each exchange wait makes before it gives
- * up and yields NaN (which reaches the costs and the non-finite status flag)
- * and sets GPMPPI_FLAG_EXCHANGE_TIMEOUT.
- * 0 restores the default (2^18 polls, about 0.3 s); a negative value makes
- * every wait give up at once, so every cost of a split launch is NaN: a hook for
- * tests of the failure path.  Takes effect from the next launch. */
+ * up.  A workgroup whose wait gives up (its partner is not running, for
+ * instance because other work holds the device) abandons the exchange,
+ * computes its sample block alone from step 0 by the unsplit rollout's code
+ * (the same results bit for bit, at about twice that workgroup's time) and
+ * sets GPMPPI_FLAG_EXCHANGE_TIMEOUT.  0 restores the default (2^18 polls,
+ * about 0.3 s); a negative value makes every wait give up at once, so every
+ * block of a split launch runs alone: a hook for tests of that path.  Takes
+ * effect from the next launch. */
 gpmppi_status gpmppi_set_exchange_spin(gpmppi_ctx *ctx, int32_t polls);
 /* Installs a shape (wg_per_cu and order are ignored for a context). */
 gpmppi_status gpmppi_set_tuning(gpmppi_ctx *ctx, const gpmppi_tuning *t);
@@ -340,7 +343,8 @@ gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uin
 /* Reads and clears the context's device status bits:
  *   GPMPPI_FLAG_NONFINITE         a weights/update call saw a non-finite cost;
  *   GPMPPI_FLAG_EXCHANGE_TIMEOUT  an exchange wait of an output-split rollout
- *                                 gave up (its samples' costs are NaN).
+ *                                 gave up and its workgroup computed its block
+ *                                 alone (results unchanged, time lost).
  * Synchronises the device. */
 #define GPMPPI_FLAG_NONFINITE 1u
 #define GPMPPI_FLAG_EXCHANGE_TIMEOUT 2u

@@ -79,6 +79,8 @@ struct RolloutArgs {
     uint32_t *xep;
     int xspin;                      // polls per exchange wait before it gives up; < 0: give up at once
     uint32_t *flags;                // context status word: GPMPPI_FLAG_EXCHANGE_TIMEOUT is set here
+    uint32_t *repair;               // [nblk] split launches: blocks whose exchange gave up, recomputed and
+                                    // cleared by the repair launch that follows (all 0 between launches)
 };
 
 struct UpdateArgs {
@@ -98,7 +100,8 @@ size_t rollout_lds_bytes(int precision, int G, int Mpad);
 // largest sample-group count whose LDS plan fits a compute unit (1 or 2)
 int rollout_groups(int precision, int Mpad);
 // G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8).
-// split = 1: each sample block's two GP outputs on two workgroups (G = 1 only; a.xrec, a.xep set),
+// split = 1: each sample block's two GP outputs on two workgroups (G = 1 only; a.xrec, a.xep, a.repair
+// set), then a repair launch of the unsplit kernel for blocks whose exchange gave up;
 // hipErrorCooperativeLaunchTooLarge if the doubled grid cannot be resident at once.
 hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st);
 // Largest sample count whose split launch at this shape can be resident at once (0: not admissible).

@@ -394,11 +394,17 @@ __device__ __forceinline__ void rollout_block(const RolloutArgs &a, int blk, uns
 // and the step, so no flag and no store-completion wait is needed.  Slots cycle
 // over four steps (a writer runs at most two steps ahead of a slot's reader).
 // The values reach the same arithmetic as in rollout_block, so the results are
-// bitwise those of the unsplit kernel.  Both workgroups of a block must be
-// resident together (the launcher checks that the whole grid fits at once);
-// every wait is bounded (RolloutArgs::xspin polls), and a wait that times out
-// yields NaN, which surfaces as non-finite costs, and sets the exchange
-// time-out bit of the context's status word.
+// bitwise those of the unsplit kernel.  The launcher admits the shape only
+// where the whole doubled grid fits the device at once, but other work on the
+// device can still keep one role waiting: every wait is bounded
+// (RolloutArgs::xspin polls), and a workgroup whose wait gives up abandons the
+// exchange, marks its block in RolloutArgs::repair and sets the exchange
+// time-out bit of the context's status word (its partner, waiting in turn,
+// does the same).  The launcher follows every split launch with a repair
+// launch of the unsplit kernel that recomputes exactly the marked blocks (the
+// same results bit for bit) and exits at once elsewhere.
+
+constexpr int kXvFail = 3 * 32;   // xv slot of wave 0's "an exchange wait gave up" flag
 
 __device__ __forceinline__ uint32_t xch_tag(uint32_t epoch, int k) {
     return ((epoch & 0x7FFFFu) << 13) | (uint32_t)(k + 1);   // k + 1 <= 4096 < 2^13
@@ -414,7 +420,7 @@ __device__ __forceinline__ void xch_put(unsigned long long *rec, int lane, float
 
 // Every lane of the calling wave waits, for at most spin polls, for the record
 // of sample lane % 32 with this tag and returns its value (NaN once a wait of
-// this wave has timed out; spin < 0 gives up at once).
+// this wave has timed out, and broken is set; spin < 0 gives up at once).
 __device__ __forceinline__ float xch_get(const unsigned long long *rec, int lane, uint32_t tag, int spin,
                                          bool &broken) {
     if (spin < 0) broken = true;
@@ -465,6 +471,7 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
     // kind: m0, m1, s2 of output 1, squared polyline distance at x_{k+1}
     auto slot = [&](int k, int kind) { return rec + ((k & 3) * 4 + kind) * 32; };
     bool broken = false;
+    bool alone = false;   // set (uniformly) when an exchange wait gave up: the block is left to the repair
     const int spin = a.xspin;
 
     float X = a.x0[0], Y = a.x0[1], th = a.x0[2], v = a.x0[3], w_ = a.x0[4];
@@ -512,8 +519,13 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
                 if (wv == 0) {
                     const float m0 = xch_get(slot(k, 0), lane, tag, spin, broken);
                     if (lane < 32) xv[lane] = m0;
+                    if (lane == 0) xv[kXvFail] = broken ? 1.0f : 0.0f;
                 }
             });
+            if (xv[kXvFail] != 0.0f) {   // the partner did not answer: leave the block to the repair
+                alone = true;
+                break;
+            }
             if (w == 0) {
                 xch_put(slot(k, 2), lane, s21, tag);
                 if (geo.path_kind != 0) {
@@ -560,8 +572,13 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
                     xv[32 + lane] = s21p;
                     xv[64 + lane] = bestp;
                 }
+                if (lane == 0) xv[kXvFail] = broken ? 1.0f : 0.0f;
             }
         });
+        if (xv[kXvFail] != 0.0f) {   // the partner did not answer: leave the block to the repair
+            alone = true;
+            break;
+        }
         const float m1 = xv[sl];
         if (k > 0) {   // step k - 1 completed: its second variance into Sigma_ww, its lane distance, its cost
             const float s21p = xv[32 + sl];
@@ -577,21 +594,26 @@ __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int bl
         s20_prev = s20;
         if (writer) write_trace(a.trace, K, sg, k, X, Y, th, v, w_, P, m0, m1, s20, 0.0f, prev, u, false, false);
     }
-    if (role == 0) {
+    if (role == 0 && !alone) {
         const uint32_t tl = xch_tag(epoch, a.T - 1);
         const float s21p = xch_get(slot(a.T - 1, 2), lane, tl, spin, broken);
         if (geo.path_kind != 0) prev.dl = sqrtf(xch_get(slot(a.T - 1, 3), lane, tl, spin, broken));
-        add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
-        if (writer) write_deferred_trace(a.trace, K, sg, a.T - 1, s21p, prev);
-        if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
-            const float yk = cw.w_term - Sc;
-            S_ = S_ + yk;
+        alone = __syncthreads_or(broken) != 0;
+        if (!alone) {
+            add_stage_cost(cw, geo, prev, s20_prev, s21p, disc, S_, Sc);
+            if (writer) write_deferred_trace(a.trace, K, sg, a.T - 1, s21p, prev);
+            if (cw.w_term != 0.0f && !(dgoal_min <= cw.goal_tol)) {
+                const float yk = cw.w_term - Sc;
+                S_ = S_ + yk;
+            }
+            if (writer) a.costs[sg] = S_;
         }
-        if (writer) a.costs[sg] = S_;
     }
-    // a wave whose exchange wait gave up reports it in the status word
-    if (broken && lane == 0 && a.flags)
-        __hip_atomic_fetch_or(a.flags, GPMPPI_FLAG_EXCHANGE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (alone && tid == 0) {   // hand the block to the repair launch that follows
+        __hip_atomic_store(a.repair + blk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a.flags)
+            __hip_atomic_fetch_or(a.flags, GPMPPI_FLAG_EXCHANGE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // the last workgroup to finish advances the epoch for the next launch
     __syncthreads();
     if (tid == 0) {
@@ -610,11 +632,13 @@ __global__ __launch_bounds__(64 * NW) void rollout_split_kernel(RolloutArgs a) {
     __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[2 * NW * S::B];   // both loops on every wave (rollout_block_split)
     __shared__ float vred[NW * S::B];
-    __shared__ float xv[3 * 32];
+    __shared__ float xv[kXvFail + 1];
     const int role = __builtin_amdgcn_readfirstlane((int)(blockIdx.x & 1));
     rollout_block_split<PREC, NW, WALK>(a, blockIdx.x >> 1, role, lds, pred, ored, vred, xv);
 }
 
+// a.repair == NULL: every block.  Otherwise the repair launch after an output
+// split (G = 1): only the blocks the split launch marked, whose marks it clears.
 template <int PREC, int G, int NW, int WALK>
 __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
     using S = Shapes<PREC, G, NW>;
@@ -622,7 +646,10 @@ __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
     __shared__ float pred[S::rparts * S::B];
     __shared__ float ored[2 * S::lwaves * S::B];
     __shared__ float vred[NW * S::B];
+    if (a.repair && __hip_atomic_load(a.repair + blockIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
     rollout_block<PREC, G, NW, WALK>(a, blockIdx.x, lds, pred, ored, vred);
+    if (a.repair && threadIdx.x == 0)
+        __hip_atomic_store(a.repair + blockIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Persistent rollout of many independent problems: every workgroup takes
@@ -762,7 +789,7 @@ static int split_capacity_t(int Mpad) {
 
 template <int PREC, int NW, int WALK>
 static hipError_t launch_rollout_split_w(const RolloutArgs &a, hipStream_t st) {
-    if (!a.xrec || !a.xep) return hipErrorInvalidValue;
+    if (!a.xrec || !a.xep || !a.repair) return hipErrorInvalidValue;
     const size_t lds = dyn_lds_bytes<PREC, 1>(a.gp.Mpad);
     int cap = 0;
     hipError_t e = split_capacity_w<PREC, NW, WALK>(a.gp.Mpad, cap);
@@ -770,7 +797,9 @@ static hipError_t launch_rollout_split_w(const RolloutArgs &a, hipStream_t st) {
     const int nblk = (a.K + 31) / 32;
     if (2 * nblk > cap) return hipErrorCooperativeLaunchTooLarge;   // both roles of every block resident together
     hipLaunchKernelGGL((rollout_split_kernel<PREC, NW, WALK>), dim3(2 * nblk), dim3(64 * NW), lds, st, a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the repair launch: the unsplit kernel recomputes the blocks whose exchange gave up
+    return launch_rollout_w<PREC, 1, NW, WALK>(a, st);
 }
 
 template <int PREC, int NW>
@@ -824,10 +853,12 @@ hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d,
     }
 }
 
-hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st) {
-    if (G < 1 || G > groups_for(precision, a.gp.Mpad) || (NW != kWaves && NW != 8) || (split != 0 && split != 1) ||
+hipError_t launch_rollout(const RolloutArgs &args, int precision, int G, int NW, int split, hipStream_t st) {
+    if (G < 1 || G > groups_for(precision, args.gp.Mpad) || (NW != kWaves && NW != 8) || (split != 0 && split != 1) ||
         (split && G != 1))
         return hipErrorInvalidValue;
+    RolloutArgs a = args;
+    if (!split) a.repair = nullptr;   // an unsplit launch computes every block
     switch (precision) {
         case GPMPPI_FP32: return launch_rollout_p<GPMPPI_FP32>(a, G, NW, split, st);
         case GPMPPI_BF16: return launch_rollout_p<GPMPPI_BF16>(a, G, NW, split, st);

@@ -167,6 +167,7 @@ struct gpmppi_ctx {
     int split = 0;                   // 1: the two GP outputs of a sample block on two workgroups (tuned)
     unsigned long long *xrec = nullptr;   // output-split exchange records [ceil(K/32)][kXchRecPerBlock]
     uint32_t *xep = nullptr;              // output-split launch epoch and finished-workgroup count
+    uint32_t *repair = nullptr;           // output-split blocks left to the repair launch [ceil(K/32)], zero between launches
     int xspin = kXchSpin;                 // polls per output-split exchange wait
     float4 *w32 = nullptr;
     uint4 *wbh = nullptr, *wbl = nullptr;
@@ -358,6 +359,7 @@ RolloutArgs rollout_args(const gpmppi_ctx *c, const float *x0, const float *U, u
     a.xep = c->xep;
     a.xspin = c->xspin;
     a.flags = c->flags;
+    a.repair = c->repair;
     a.x0 = x0;
     a.U = U;
     a.costs = costs;
@@ -466,13 +468,16 @@ gpmppi_status gpmppi_init(const gpmppi_params *params, const gpmppi_gp gp[2], co
     const size_t nxrec = (size_t)((params->K + 31) / 32) * kXchRecPerBlock;
     c->xrec = track(dev_alloc<unsigned long long>(nxrec, st));
     c->xep = track(dev_alloc<uint32_t>(2, st));
+    const size_t nblk = (size_t)((params->K + 31) / 32);
+    c->repair = track(dev_alloc<uint32_t>(nblk, st));
     if (st != GPMPPI_OK) {
         delete c;
         return st;
     }
     if (hipMemset(c->flags, 0, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->xrec, 0, nxrec * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->xep, 0, 2 * sizeof(uint32_t)) != hipSuccess) {
+        hipMemset(c->xep, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->repair, 0, nblk * sizeof(uint32_t)) != hipSuccess) {
         delete c;
         return fail(GPMPPI_E_HIP, "hipMemset failed");
     }

@@ -130,20 +130,30 @@ def test_split_admissibility_and_tuner():
         np.testing.assert_array_equal(S_a, S_b)
 
 
-def test_split_exchange_timeout_yields_nan_and_the_next_launch_is_exact():
-    # the failure path, forced from the host: every exchange wait gives up at once, the
-    # kernel completes, every cost is NaN and the update raises the non-finite flag; the
-    # next launch (default wait) is exact again (records of the failed launch carry its epoch)
+def test_split_exchange_timeout_runs_each_block_alone_with_identical_results():
+    # the fallback path, forced from the host: every exchange wait gives up at once, so every
+    # workgroup of the split launch computes its block alone with the unsplit code; costs, U and
+    # weights equal the unsplit launch's bit for bit and the status word reports the time-out
+    # (not a non-finite cost); the next launch at the default wait is split again and exact
+    # (records of the abandoned launch carry its epoch)
     pr = W.small_problem(K=96, T=8, M=40, n_obs=3, path="eight", seed_data=211, U_scale=1.0)
     ctx = B.gpmppi_init(pr, B.FP32)
     B.gpmppi_set_tuning(ctx, 1, 1, 8, 0)
     U_a, S_a, w_a = gpu_step(pr, ctx=ctx)
+    S_ra, tr_a = gpu_rollout(pr, ctx=ctx)
     assert B.gpmppi_status_flags(ctx) == 0
     B.gpmppi_set_tuning(ctx, 1, 1, 8, 1)
     B.gpmppi_set_exchange_spin(ctx, -1)
-    _, S_b, _ = gpu_step(pr, ctx=ctx)
-    assert np.all(np.isnan(S_b))
-    assert B.gpmppi_status_flags(ctx) == B.FLAG_NONFINITE | B.FLAG_EXCHANGE_TIMEOUT
+    U_b, S_b, w_b = gpu_step(pr, ctx=ctx)
+    np.testing.assert_array_equal(S_b, S_a)
+    np.testing.assert_array_equal(U_b, U_a)
+    np.testing.assert_array_equal(w_b, w_a)
+    assert B.gpmppi_status_flags(ctx) == B.FLAG_EXCHANGE_TIMEOUT
+    S_rb, tr_b = gpu_rollout(pr, ctx=ctx)
+    np.testing.assert_array_equal(S_rb, S_ra)
+    for key in tr_a:
+        np.testing.assert_array_equal(tr_b[key], tr_a[key], err_msg=key)
+    assert B.gpmppi_status_flags(ctx) == B.FLAG_EXCHANGE_TIMEOUT
     B.gpmppi_set_exchange_spin(ctx, 0)
     U_c, S_c, w_c = gpu_step(pr, ctx=ctx)
     np.testing.assert_array_equal(S_c, S_a)
