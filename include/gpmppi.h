@@ -234,6 +234,16 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, 
                           int32_t checkpoint_every, float *J_d, float *dU_d, float *dlog_ell_d, float *dlog_sf_d,
                           float *costs_d, void *stream);
 
+/* The gradient's launch shape: split = 1 (the default) runs each 32-sample
+ * block's two GP outputs on two workgroups that exchange, per step, their
+ * output's mean and variance (forward) and their share of the GP inputs'
+ * adjoint (backward), wherever the doubled grid fits the device at once
+ * (K <= 4096 at M <= 512 on MI355X); 0 keeps one workgroup per block.  The
+ * results do not depend on it (bit for bit).  Exchange waits are bounded as
+ * for the rollout (gpmppi_set_exchange_spin); a block whose wait gives up is
+ * recomputed by a repair launch and GPMPPI_FLAG_EXCHANGE_TIMEOUT is set. */
+gpmppi_status gpmppi_set_grad_split(gpmppi_ctx *ctx, int32_t split);
+
 /* Allocation-free gpmppi_grad, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same arguments, computation and results, with the

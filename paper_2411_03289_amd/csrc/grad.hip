@@ -8,7 +8,15 @@
 // A^-1, A = K(Z, Z) + sn^2 I).
 //
 // grad_kernel: one workgroup of 256 threads per 32 samples (one 32-column
-// matrix-core group; 8 loop parts = 4 waves x 2 half-waves).
+// matrix-core group; 8 loop parts = 4 waves x 2 half-waves), or, split, two
+// workgroups per 32 samples, workgroup 2 blk + r doing the GP work of output r
+// (kernel vectors, variance walk, r = Q k and its sums) and both doing the
+// per-sample algebra; they exchange, per forward step, their output's GP mean
+// and variance and, per reversed step, their output's share of the GP inputs'
+// adjoint.  The exchanged values enter the same arithmetic in the same order
+// as in the unsplit kernel, so the results are the same bit for bit.  A
+// workgroup whose bounded exchange wait gives up marks its block for the
+// repair launch of the unsplit kernel that follows every split launch.
 //   job 0   forward over all T steps: costs, the state (x, Sigma) every C
 //           steps (checkpoints), and the last segment's per-step record;
 //   job j   for segment n - j (last first): recompute the segment's C steps
@@ -212,8 +220,18 @@ __device__ __forceinline__ void constraint_scan(const Geometry &geo, float X, fl
 
 __device__ __forceinline__ void seg_put(float *base, int f, float v) { base[f * kB] = v; }
 
+// a + b, never fused with the product that formed b: the split kernel adds the
+// partner's share after receiving it as a value, and the unsplit kernel must round alike.
+__device__ __forceinline__ float add_rounded(float a, float b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+
 }  // namespace
 
+// SPLIT: role = blockIdx.x & 1 of block blockIdx.x >> 1 (see above).  REPAIR
+// (unsplit): the repair launch, only the blocks a split launch marked.
+template <bool SPLIT, bool REPAIR = false>
 __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ float pred[kParts * kB];
@@ -222,12 +240,15 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     __shared__ int ib[kParts * kB], io[kParts * kB];
     __shared__ __align__(16) float gred[11 * kParts * kB];
     __shared__ float mb_s[2][kB], sb_s[2][kB], ub_s[2][kB];
+    __shared__ float xv[5 * kB + 1];   // split: values received from the partner, and a give-up flag
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int sl = lane & 31;
     const int part = 2 * w + (lane >> 5);
-    const int blk = blockIdx.x;
+    const int blk = SPLIT ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
+    const int role = SPLIT ? (int)(blockIdx.x & 1) : 0;   // split: the GP output this workgroup computes
+    if (REPAIR && __hip_atomic_load(a.repair + blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
     const int sg = blk * kB + sl;
     const bool valid = sg < a.K;
     const bool writer = w == 0 && lane < kB;   // one copy of each sample
@@ -239,10 +260,22 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
     const Dyn dy = a.dyn;
     const float dt = dy.dt;
     const float cbar = valid ? a.inv_K : 0.0f;
-    float *segw = a.seg + (size_t)blk * (C + 1) * kSegF * kB + sl;   // [e][f][32]
+    // per-(block, role) segment scratch [e][f][32] and per-role checkpoints
+    float *segw = a.seg + ((size_t)blk * 2 + role) * (C + 1) * kSegF * kB + sl;
+    float *ckpt = a.ckpt + (size_t)role * a.nck * kCkF * K;
     float *rb = reinterpret_cast<float *>(lds + grad_rbuf_off(Mpad));
 
     NoiseParams np = a.noise;
+
+    // split exchange: event e (the same sequence in both roles) uses slot e % 4 of the
+    // writer's records [block][writer role][slot][kind][32]; records are zeroed before
+    // the launch, and the tag e + 1 names the event
+    unsigned long long *xrec = SPLIT ? a.xrec + (size_t)blk * kGradXchPerBlock : nullptr;
+    auto xslot = [&](int wr, uint32_t e, int kind) {
+        return xrec + ((size_t)(wr * 4 + (int)(e & 3u)) * 4 + kind) * kB;
+    };
+    uint32_t ev = 0;
+    bool broken = false, alone = false;
 
     // per-sample accumulators of the hyperparameter terms through k (o, theta)
     double hyp[2][5] = {};
@@ -271,18 +304,18 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
 #pragma unroll
             for (int i = 0; i < 15; ++i) p[i] = 0.0f;
         } else {
-            const float *ck = a.ckpt + (size_t)segi * kCkF * K + (valid ? sg : 0);
+            const float *ck = ckpt + (size_t)segi * kCkF * K + (valid ? sg : 0);
             X = ck[0 * (size_t)K]; Y = ck[1 * (size_t)K]; th = ck[2 * (size_t)K]; v = ck[3 * (size_t)K];
             w_ = ck[4 * (size_t)K];
 #pragma unroll
             for (int i = 0; i < 15; ++i) p[i] = ck[(5 + i) * (size_t)K];
         }
-        restage(g, (k0 & 1) ? 1 : 0, lds);
+        restage(g, SPLIT ? role : ((k0 & 1) ? 1 : 0), lds);
         // ---------------------------------------------------------- forward
         for (int k = k0; k < kf; ++k) {
             if (writer) {
                 if (first && k % C == 0 && valid) {
-                    float *ck = a.ckpt + (size_t)(k / C) * kCkF * K + sg;
+                    float *ck = ckpt + (size_t)(k / C) * kCkF * K + sg;
                     ck[0 * (size_t)K] = X; ck[1 * (size_t)K] = Y; ck[2 * (size_t)K] = th; ck[3 * (size_t)K] = v;
                     ck[4 * (size_t)K] = w_;
 #pragma unroll
@@ -299,14 +332,42 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
             const float q[4] = {v, w_, u.x, u.y};
             float m[2], s2[2];
-#pragma unroll
-            for (int oo = 0; oo < 2; ++oo) {
-                const int o = rev ? 1 - oo : oo;
+            if constexpr (SPLIT) {   // this role's output, then the partner's mean and variance
+                const int o = role;
                 __syncthreads();
                 const float qs[4] = {q[0] * g.scale[o][0], q[1] * g.scale[o][1], q[2] * g.scale[o][2],
                                      q[3] * g.scale[o][3]};
-                gp_output<GPMPPI_FP32, 1>(g, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, 0, blk, lds, pred, vred,
-                                          m[o], s2[o]);
+                gp_output<GPMPPI_FP32, 1>(g, o, -1, qs, part, sl, rev, 0, blk, lds, pred, vred, m[o], s2[o]);
+                const uint32_t tag = ev + 1;
+                if (w == 0) {
+                    xch_put(xslot(role, ev, 0), lane, m[o], tag);
+                    xch_put(xslot(role, ev, 1), lane, s2[o], tag);
+                    const float mp = xch_get(xslot(1 - role, ev, 0), lane, tag, a.xspin, broken);
+                    const float sp = xch_get(xslot(1 - role, ev, 1), lane, tag, a.xspin, broken);
+                    if (lane < kB) {
+                        xv[lane] = mp;
+                        xv[kB + lane] = sp;
+                    }
+                    if (lane == 0) xv[5 * kB] = broken ? 1.0f : 0.0f;
+                }
+                ++ev;
+                __syncthreads();
+                if (xv[5 * kB] != 0.0f) {
+                    alone = true;
+                    break;
+                }
+                m[1 - o] = xv[sl];
+                s2[1 - o] = xv[kB + sl];
+            } else {
+#pragma unroll
+                for (int oo = 0; oo < 2; ++oo) {
+                    const int o = rev ? 1 - oo : oo;
+                    __syncthreads();
+                    const float qs[4] = {q[0] * g.scale[o][0], q[1] * g.scale[o][1], q[2] * g.scale[o][2],
+                                         q[3] * g.scale[o][3]};
+                    gp_output<GPMPPI_FP32, 1>(g, o, oo == 0 ? 1 - o : -1, qs, part, sl, rev, 0, blk, lds, pred,
+                                              vred, m[o], s2[o]);
+                }
             }
             float sth, cth;
             sincosf(th, &sth, &cth);
@@ -345,8 +406,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                 disc *= cw.discount;
             }
         }
+        if (alone) break;
         if (first) {
-            if (writer && valid) a.costs[sg] = S_;
+            if (writer && valid && role == 0) a.costs[sg] = S_;
             if (writer) {   // the last segment's final state
                 float *e = segw + (size_t)(T - kl0) * kSegF * kB;
                 seg_put(e, 0, X); seg_put(e, 1, Y); seg_put(e, 2, th); seg_put(e, 3, v); seg_put(e, 4, w_);
@@ -401,7 +463,9 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             // ---- GP adjoint, both outputs
             const float qk[4] = {vk, wk, ux, uy};
             float qb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float qown[4];   // split: this role's output's share of the GP inputs' adjoint
             for (int o = 0; o < 2; ++o) {
+                if (SPLIT && o != role) continue;
                 const float sbo = s2b[o] * flag[o];
                 if (writer) {
                     mb_s[o][sl] = mb[o];
@@ -476,13 +540,41 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                 }
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    qb[d] += 2.0f * kLn2 * g.scale[o][d] * tot[1 + d];
+                    const float qd = 2.0f * kLn2 * g.scale[o][d] * tot[1 + d];
+                    if constexpr (SPLIT) qown[d] = qd;
+                    else qb[d] = add_rounded(qb[d], qd);
                     hyp[o][d] += (double)(-2.0f * kLn2 * tot[5 + d]);
                 }
                 {   // log sf: the folded per-sample terms (k and A^-1 parts cancelled)
                     const double sn2 = (double)g.sn2[o];
                     hyp[o][4] += 2.0 * (double)sbo * (((double)s2k[o] - sn2) - sn2 * (double)tot[9]) +
                                  2.0 * sn2 * (double)mb[o] * (double)tot[10];
+                }
+            }
+            if constexpr (SPLIT) {   // the partner's share, received in exchange for ours
+                const uint32_t tag = ev + 1;
+                if (w == 0) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) xch_put(xslot(role, ev, d), lane, qown[d], tag);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const float vq = xch_get(xslot(1 - role, ev, d), lane, tag, a.xspin, broken);
+                        if (lane < kB) xv[d * kB + lane] = vq;
+                    }
+                    if (lane == 0) xv[5 * kB] = broken ? 1.0f : 0.0f;
+                }
+                ++ev;
+                __syncthreads();
+                if (xv[5 * kB] != 0.0f) {
+                    alone = true;
+                    break;
+                }
+                // in output order, as the unsplit kernel accumulates them
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const float qp = xv[d * kB + sl];
+                    qb[d] = add_rounded(qb[d], role == 0 ? qown[d] : qp);
+                    qb[d] = add_rounded(qb[d], role == 0 ? qp : qown[d]);
                 }
             }
             vbk += qb[0];
@@ -500,7 +592,7 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
                     ub_s[1][sl] = valid ? uyb * m1 : 0.0f;
                 }
                 __syncthreads();
-                if (tid < 2) {
+                if (tid < 2 && role == 0) {
                     float sum = 0.0f;
                     for (int i = 0; i < kB; ++i) sum += ub_s[tid][i];
                     a.upart[((size_t)blk * T + k) * 2 + tid] = sum;
@@ -509,9 +601,19 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             xb[3] = vbk;
             xb[4] = wbk;
         }
+        if (alone) break;
     }
     (void)np;
-    // ---- per-workgroup partial sums
+    if (SPLIT && alone) {   // uniform: leave the block to the repair launch
+        if (tid == 0) {
+            __hip_atomic_store(a.repair + blk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.flags)
+                __hip_atomic_fetch_or(a.flags, GPMPPI_FLAG_EXCHANGE_TIMEOUT, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    // ---- per-workgroup partial sums (split: this role's output only)
     __syncthreads();
     double *hred = reinterpret_cast<double *>(gred);   // 10 x 32 doubles
     if (writer) {
@@ -521,16 +623,28 @@ __global__ __launch_bounds__(kThreads) void grad_kernel(GradArgs a) {
             for (int i = 0; i < 5; ++i) hred[(o * 5 + i) * kB + sl] = valid ? hyp[o][i] : 0.0;
     }
     __syncthreads();
-    if (tid < 10) {
+    if (tid < 10 && (!SPLIT || tid / 5 == role)) {
         double s = 0.0;
         for (int i = 0; i < kB; ++i) s += hred[tid * kB + i];
         a.hpart[(size_t)blk * 10 + tid] = s;
     }
-    for (int o = 0; o < 2; ++o)
+    for (int o = 0; o < 2; ++o) {
+        if (SPLIT && o != role) continue;
         for (int jj = 0; jj < 2; ++jj) {
             const int j = tid + kThreads * jj;
             if (j < Mpad) a.bpart[((size_t)blk * 2 + o) * Mpad + j] = bacc[o][jj];
         }
+    }
+    if (REPAIR && tid == 0)   // the block is done
+        __hip_atomic_store(a.repair + blk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Zeroes the split gradient's exchange records and repair marks before a launch.
+__global__ __launch_bounds__(kThreads) void grad_clear_kernel(unsigned long long *rec, size_t n_rec, uint32_t *repair,
+                                                              int n_blk) {
+    const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n_rec) rec[i] = 0ull;
+    if (i < (size_t)n_blk) repair[i] = 0u;
 }
 
 
@@ -721,12 +835,46 @@ __global__ __launch_bounds__(kThreads) void grad_final_kernel(const float *costs
 
 size_t grad_lds(int Mpad) { return grad_lds_bytes(Mpad); }
 
-hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st) {
-    const size_t lds = grad_lds_bytes(a.gp.Mpad);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grad_kernel, dim3(l.nwg), dim3(kThreads), lds, st, a);
+int grad_split_capacity(int Mpad) {
+    const size_t lds = grad_lds_bytes(Mpad);
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(grad_kernel<true>),
+                                                     kThreads, lds) != hipSuccess)
+        return 0;
+    return per_cu * ncu;
+}
+
+hipError_t launch_grad(const GradArgs &args, const GradLaunch &l, hipStream_t st) {
+    const size_t lds = grad_lds_bytes(args.gp.Mpad);
+    GradArgs a = args;
+    hipError_t e;
+    if (a.split) {
+        if (!a.xrec || !a.repair || 2 * l.nwg > grad_split_capacity(a.gp.Mpad)) return hipErrorInvalidValue;
+        const size_t n_rec = (size_t)l.nwg * kGradXchPerBlock;
+        const size_t n = n_rec > (size_t)l.nwg ? n_rec : (size_t)l.nwg;
+        hipLaunchKernelGGL(grad_clear_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                           a.xrec, n_rec, a.repair, l.nwg);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(grad_kernel<true>, dim3(2 * l.nwg), dim3(kThreads), lds, st, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // the repair launch: the unsplit kernel for the blocks whose exchange gave up
+        if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel<false, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((grad_kernel<false, true>), dim3(l.nwg), dim3(kThreads), lds, st, a);
+    } else {
+        if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(grad_kernel<false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(grad_kernel<false>, dim3(l.nwg), dim3(kThreads), lds, st, a);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const long long TK = (long long)a.T * a.K;
     hipLaunchKernelGGL(grad_syrk_kernel, dim3(l.npairs, l.nsplit, 2), dim3(kThreads), 0, st, a.R, a.Gw, TK, a.gp.Mpad,

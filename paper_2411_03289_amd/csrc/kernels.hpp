@@ -180,6 +180,14 @@ struct GradArgs {
     double *bpart;           // [nwg][2][Mpad]
     double *hpart;           // [nwg][10]
     float *upart;            // [nwg][T][2]
+    // output split (two workgroups per 32 samples, one per GP output): ckpt holds [2 roles]
+    // and seg [nwg][2 roles] copies; xrec [nwg][kGradXchPerBlock] exchange records, zeroed
+    // with repair [nwg] before each split launch; repair marks blocks for the repair launch
+    int split;
+    unsigned long long *xrec;
+    uint32_t *repair;
+    int xspin;               // polls per exchange wait before it gives up; < 0: give up at once
+    uint32_t *flags;         // context status word (GPMPPI_FLAG_EXCHANGE_TIMEOUT)
 };
 
 struct GradLaunch {
@@ -191,6 +199,9 @@ struct GradLaunch {
 };
 // Dynamic LDS of grad_kernel at this Mpad (must be <= 160 KB minus its static LDS).
 size_t grad_lds(int Mpad);
+constexpr int kGradXchPerBlock = 2 * 4 * 4 * kSamplesPerBlock;   // split exchange records per block
+// Workgroups of the split gradient kernel resident at once (a split launch needs 2 nwg).
+int grad_split_capacity(int Mpad);
 hipError_t launch_grad(const GradArgs &a, const GradLaunch &l, hipStream_t st);
 
 // Q = A^-1 = W^T W packed dense (FP32 operand order); overwrites b.A.

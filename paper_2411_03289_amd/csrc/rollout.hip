@@ -410,34 +410,6 @@ __device__ __forceinline__ uint32_t xch_tag(uint32_t epoch, int k) {
     return ((epoch & 0x7FFFFu) << 13) | (uint32_t)(k + 1);   // k + 1 <= 4096 < 2^13
 }
 
-// Lanes 0..31 of the calling wave publish their sample's value.
-__device__ __forceinline__ void xch_put(unsigned long long *rec, int lane, float val, uint32_t tag) {
-    if (lane < 32) {
-        const unsigned long long r = ((unsigned long long)tag << 32) | __float_as_uint(val);
-        __hip_atomic_store(rec + lane, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Every lane of the calling wave waits, for at most spin polls, for the record
-// of sample lane % 32 with this tag and returns its value (NaN once a wait of
-// this wave has timed out, and broken is set; spin < 0 gives up at once).
-__device__ __forceinline__ float xch_get(const unsigned long long *rec, int lane, uint32_t tag, int spin,
-                                         bool &broken) {
-    if (spin < 0) broken = true;
-    if (broken) return __builtin_nanf("");
-    unsigned long long r = 0;
-    for (int n = 0;; ++n) {
-        r = __hip_atomic_load(rec + (lane & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__all((uint32_t)(r >> 32) == tag)) break;
-        if (n == spin) {
-            broken = true;
-            return __builtin_nanf("");
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return __uint_as_float((uint32_t)r);
-}
-
 // Role `role` of sample block blk (one sample group, G = 1); see above.
 template <int PREC, int NW, int WALK>
 __device__ __forceinline__ void rollout_block_split(const RolloutArgs &a, int blk, int role, unsigned char *lds,

@@ -176,6 +176,7 @@ struct gpmppi_ctx {
     float4 *q32 = nullptr;           // dense packed Q = A^-1 per output (differentiation form, Mpad <= 512)
     long long q_stride = 0;          // float4 per output
     void *grad_ws = nullptr;         // differentiation-form workspace (grown on demand)
+    int grad_split = 1;              // 1: split the gradient's outputs over two workgroups where they fit
     size_t grad_ws_bytes = 0;
     void *scratch = nullptr;         // this device's allocation-free scratch array (not owned)
     float4 *obs = nullptr;
@@ -1166,7 +1167,9 @@ namespace {
 struct GradLayout {
     GradLaunch l{};
     int C = 1, nck = 1;
+    int split = 0;   // two workgroups per 32 samples, one per GP output (when they fit the device at once)
     size_t o_ck = 0, o_seg = 0, o_R = 0, o_G = 0, o_b = 0, o_h = 0, o_u = 0, o_p = 0, o_bt = 0, o_c = 0;
+    size_t o_x = 0, o_rp = 0;
     size_t bytes = 0;
 };
 
@@ -1200,8 +1203,9 @@ gpmppi_status grad_check(const gpmppi_ctx *c, const float *x0_d, const float *U_
         off += (nfloat * sizeof(float) + 255) / 256 * 256;
         return at;
     };
-    g.o_ck = take((size_t)g.nck * 20 * K);
-    g.o_seg = take((size_t)l.nwg * (g.C + 1) * 28 * 32);
+    g.split = c->grad_split && 2 * l.nwg <= grad_split_capacity(Mpad) ? 1 : 0;
+    g.o_ck = take((size_t)2 * g.nck * 20 * K);                  // one copy per role
+    g.o_seg = take((size_t)l.nwg * 2 * (g.C + 1) * 28 * 32);    // per block and role
     g.o_R = take((size_t)2 * TK * Mpad);
     g.o_G = take((size_t)2 * TK);
     g.o_b = take((size_t)l.nwg * 2 * Mpad * 2);
@@ -1210,6 +1214,8 @@ gpmppi_status grad_check(const gpmppi_ctx *c, const float *x0_d, const float *U_
     g.o_p = take((size_t)2 * l.npairs * l.nsplit * 4 * 2);
     g.o_bt = take((size_t)2 * l.nbterm * 4 * 2);
     g.o_c = take((size_t)K);
+    g.o_x = take((size_t)l.nwg * kGradXchPerBlock * 2);         // 64-bit exchange records
+    g.o_rp = take((size_t)l.nwg);
     g.bytes = off;
     return GPMPPI_OK;
 }
@@ -1248,6 +1254,11 @@ gpmppi_status grad_enqueue(const gpmppi_ctx *c, const GradLayout &g, char *ws, c
     a.upart = reinterpret_cast<float *>(ws + g.o_u);
     l.ppart = reinterpret_cast<double *>(ws + g.o_p);
     l.bterm = reinterpret_cast<double *>(ws + g.o_bt);
+    a.split = g.split;
+    a.xrec = reinterpret_cast<unsigned long long *>(ws + g.o_x);
+    a.repair = reinterpret_cast<uint32_t *>(ws + g.o_rp);
+    a.xspin = c->xspin;
+    a.flags = c->flags;
     l.J = J_d;
     l.dU = dU_d;
     l.dlog_ell = dlog_ell_d;
@@ -1279,6 +1290,14 @@ gpmppi_status gpmppi_grad(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     }
     return grad_enqueue(c, g, static_cast<char *>(c->grad_ws), x0_d, U_d, seed, tau, J_d, dU_d, dlog_ell_d,
                         dlog_sf_d, costs_d, (hipStream_t)stream);
+}
+
+gpmppi_status gpmppi_set_grad_split(gpmppi_ctx *c, int32_t split) {
+    g_last_error.clear();
+    if (!c) return fail(GPMPPI_E_INVALID, "ctx is NULL");
+    if (split != 0 && split != 1) return fail(GPMPPI_E_INVALID, "split must be 0 or 1 (got %d)", split);
+    c->grad_split = split;
+    return GPMPPI_OK;
 }
 
 gpmppi_status gpmppi_grad_noalloc(gpmppi_ctx *c, const float *x0_d, const float *U_d, uint64_t seed, double tau,

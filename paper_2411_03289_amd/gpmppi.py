@@ -114,6 +114,7 @@ def lib() -> ctypes.CDLL:
         "gpmppi_grad_noalloc": [vp, vp, vp, u64, f64, i32, vp, vp, vp, vp, vp, vp],
         "gpmppi_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_set_exchange_spin": [vp, i32],
+        "gpmppi_set_grad_split": [vp, i32],
         "gpmppi_get_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
         "gpmppi_batch_tune": [vp, vp, vp, u64, i32, ctypes.POINTER(gpmppi_tuning), vp],
         "gpmppi_batch_set_tuning": [vp, ctypes.POINTER(gpmppi_tuning)],
@@ -542,6 +543,10 @@ def gpmppi_set_tuning(ctx: Context, groups: int, rotate: int, waves: int = 4, sp
 
 def gpmppi_set_exchange_spin(ctx: Context, polls: int):
     _check(lib().gpmppi_set_exchange_spin(ctx.handle, polls))
+
+
+def gpmppi_set_grad_split(ctx: Context, split: int):
+    _check(lib().gpmppi_set_grad_split(ctx.handle, int(split)))
 
 
 def gpmppi_get_tuning(ctx: Context) -> dict:

@@ -91,6 +91,38 @@ def test_checkpoint_interval_does_not_change_results():
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["ragged", "c4_small", "one_block"])
+def test_output_split_equals_one_workgroup_per_block(case):
+    """Two workgroups per 32-sample block, one per GP output, exchanging means, variances and the GP
+    inputs' adjoint shares: J, every gradient block and every smoothed cost equal the unsplit
+    launch's bit for bit; with every exchange wait forced to give up, the repair launch recomputes
+    every block (same bits) and the status word reports the time-out."""
+    if case == "ragged":
+        pr, C = W.small_problem(K=70, T=11, M=64, n_obs=5, path="eight", seed_data=64, U_scale=1.0), 4
+    elif case == "c4_small":
+        pr, C = _c4_small(), 10
+    else:
+        pr, C = W.small_problem(K=17, T=6, M=40, n_obs=2, seed_data=66, U_scale=0.5), 6
+    ctx = B.gpmppi_init(pr, B.FP32)
+    B.gpmppi_set_grad_split(ctx, 0)
+    ref = _run(pr, pr.seed, C=C, ctx=ctx)
+    B.gpmppi_set_grad_split(ctx, 1)
+    got = _run(pr, pr.seed, C=C, ctx=ctx)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(b, a)
+    assert B.gpmppi_status_flags(ctx) == 0
+    B.gpmppi_set_exchange_spin(ctx, -1)
+    forced = _run(pr, pr.seed, C=C, ctx=ctx)
+    for a, b in zip(ref, forced):
+        np.testing.assert_array_equal(b, a)
+    assert B.gpmppi_status_flags(ctx) == B.FLAG_EXCHANGE_TIMEOUT
+    B.gpmppi_set_exchange_spin(ctx, 0)
+    again = _run(pr, pr.seed, C=C, ctx=ctx)
+    for a, b in zip(ref, again):
+        np.testing.assert_array_equal(b, a)
+    assert B.gpmppi_status_flags(ctx) == 0
+
+
 def test_autograd_function_returns_the_adjoint_gradient():
     t = torch()
     pr = W.small_problem(K=64, T=8, M=48, n_obs=4, seed_data=65, U_scale=1.0)
