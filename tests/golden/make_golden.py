@@ -19,9 +19,8 @@ the iteration starts from, the warm-started controls U_t [T,2] it is given,
 its result U'_t [T,2] (Philox key seed + t), and the number of samples with
 an indicator margin within 1e-4 m of its threshold; then the plant step with
 U'_t[0] (amplitude 0.3) and the shift.  For the steps that have such samples
-(flagged_steps) it also keeps max S and, for every sample whose weight could
-exceed exp(-40) once its near-threshold indicators flip, (step, sample id,
-S, flip budget) as flagged_rows [n, 4].
+(flagged_steps) it also keeps max S (S_max) and (step, sample id, flip budget)
+of each such sample as flagged_rows [n, 3].
 
     python tests/golden/make_golden.py c4
 
@@ -85,8 +84,7 @@ def golden_c1(n_steps=100, amplitude=0.3):
         if n_flag[-1]:
             flagged_steps.append(t)
             S_max.append(S.max())
-            keep = np.nonzero((S - flip - S.min()) / p["lam"] <= 40.0)[0]
-            rows.extend([(t, i, S[i], flip[i]) for i in keep])
+            rows.extend([(t, i, flip[i]) for i in np.nonzero(flip > 0)[0]])
         U_out.append(U_new)
         x = D.plant_step(x, U_new[0], p["dt"], p["tau_v"], p["tau_w"], amplitude)[0]
         U = mppi.shift(U_new)
@@ -94,7 +92,7 @@ def golden_c1(n_steps=100, amplitude=0.3):
     xs.append(x.copy())
     np.savez_compressed(os.path.join(HERE, "c1_loop.npz"), x=np.array(xs), U_in=np.array(U_in),
                         U_out=np.array(U_out), n_flag=np.array(n_flag), flagged_steps=np.array(flagged_steps, int),
-                        S_max=np.array(S_max), flagged_rows=np.array(rows, dtype=np.float64).reshape(-1, 4),
+                        S_max=np.array(S_max), flagged_rows=np.array(rows, dtype=np.float64).reshape(-1, 3),
                         amplitude=amplitude, flip_band=FLIP_BAND)
 
 
