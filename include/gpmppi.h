@@ -272,7 +272,11 @@ typedef struct {
     int32_t rotate;      /* 1: each workgroup starts its walk over W at a block-dependent row-pair; 0: at pair 0 */
     int32_t wg_per_cu;   /* batches: persistent workgroups per compute unit, 1 or 2 (LDS permitting) */
     int32_t order;       /* batches: 0 = items longest first, 1 = problem order */
-    int32_t waves;       /* wave64s per rollout workgroup: 4 or 8 */
+    int32_t waves;       /* wave64s per rollout workgroup: 4 or 8, or 12 for the wave-specialised
+                          * rollout of the BF16 forms at M_pad = 1024 (contexts, groups = the largest
+                          * that fits: eight waves stream W through the matrix cores while four
+                          * generate the next kernel vectors on the VALU and carry the sample state,
+                          * handing the k operand over column tile by column tile in LDS) */
     int32_t split;       /* contexts: 1 runs the two GP outputs of each 32-sample block on two workgroups
                           * that exchange means and variances every step (groups = 1, and only where the
                           * doubled grid fits the device at once; results equal those of split = 0);
@@ -354,10 +358,15 @@ gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uin
  *   GPMPPI_FLAG_NONFINITE         a weights/update call saw a non-finite cost;
  *   GPMPPI_FLAG_EXCHANGE_TIMEOUT  an exchange wait of an output-split rollout
  *                                 gave up and its workgroup computed its block
- *                                 alone (results unchanged, time lost).
+ *                                 alone (results unchanged, time lost);
+ *   GPMPPI_FLAG_PIPELINE_STALL    a hand-over wait inside a wave-specialised
+ *                                 rollout workgroup (waves = 12) gave up, which
+ *                                 only a defect can cause: that workgroup's
+ *                                 costs are NaN.
  * Synchronises the device. */
 #define GPMPPI_FLAG_NONFINITE 1u
 #define GPMPPI_FLAG_EXCHANGE_TIMEOUT 2u
+#define GPMPPI_FLAG_PIPELINE_STALL 4u
 gpmppi_status gpmppi_status_flags(gpmppi_ctx *ctx, uint32_t *flags);
 
 /* Derived scalars of a context: M_pad (M rounded up to a multiple of 64),

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgpmppi.so")
-SOURCES = ["rollout.hip", "update.hip", "gp_build.hip", "grad.hip", "runtime.cpp", "terrain.cpp"]
+SOURCES = ["rollout.hip", "rollout_pipe.hip", "update.hip", "gp_build.hip", "grad.hip", "runtime.cpp", "terrain.cpp"]
 ARCH = os.environ.get("GPMPPI_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

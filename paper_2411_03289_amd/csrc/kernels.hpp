@@ -99,13 +99,19 @@ struct UpdateArgs {
 size_t rollout_lds_bytes(int precision, int G, int Mpad);
 // largest sample-group count whose LDS plan fits a compute unit (1 or 2)
 int rollout_groups(int precision, int Mpad);
-// G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8).
+// G sample groups of 32 per workgroup (<= rollout_groups), NW wave64s per workgroup (4 or 8; 12: the
+// wave-specialised rollout, where rollout_pipe_admissible).
 // split = 1: each sample block's two GP outputs on two workgroups (G = 1 only; a.xrec, a.xep, a.repair
 // set), then a repair launch of the unsplit kernel for blocks whose exchange gave up;
 // hipErrorCooperativeLaunchTooLarge if the doubled grid cannot be resident at once.
 hipError_t launch_rollout(const RolloutArgs &a, int precision, int G, int NW, int split, hipStream_t st);
 // Largest sample count whose split launch at this shape can be resident at once (0: not admissible).
 int rollout_split_capacity(int precision, int Mpad, int NW);
+// Wave-specialised rollout (twelve waves: eight walk W, four generate the kernel vectors and carry
+// the sample state): the BF16 forms at Mpad = 1024 with the largest group count only.
+constexpr int kPipeWaves = 12;
+bool rollout_pipe_admissible(int precision, int G, int Mpad);
+hipError_t launch_rollout_pipe(const RolloutArgs &a, int precision, int G, hipStream_t st);
 constexpr int kXchRecPerBlock = 4 * 4 * 32;   // exchange records per sample block
 constexpr int kXchSpin = 1 << 18;               // default polls of an exchange wait (~0.3 s)
 hipError_t launch_rollout_batch(const RolloutArgs *probs_d, const int2 *items_d, int n_items, uint32_t *counter,

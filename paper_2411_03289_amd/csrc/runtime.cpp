@@ -803,7 +803,10 @@ bool split_admissible(const gpmppi_ctx *c, int waves) {
 
 gpmppi_status check_tuning(const gpmppi_tuning *t, int G_max, int wg_max, bool batch) {
     if (!t) return fail(GPMPPI_E_INVALID, "tuning is NULL");
-    if (t->waves != 4 && t->waves != 8) return fail(GPMPPI_E_INVALID, "waves must be 4 or 8 (got %d)", t->waves);
+    if (t->waves != 4 && t->waves != 8 && t->waves != kPipeWaves)
+        return fail(GPMPPI_E_INVALID, "waves must be 4, 8 or %d (got %d)", kPipeWaves, t->waves);
+    if (t->waves == kPipeWaves && batch) return fail(GPMPPI_E_INVALID, "batches run 4 or 8 waves per workgroup");
+    if (t->waves == kPipeWaves && t->split) return fail(GPMPPI_E_INVALID, "the wave-specialised rollout does not split outputs");
     if (t->groups < 1 || t->groups > G_max)
         return fail(GPMPPI_E_INVALID, "groups must lie in [1, %d] here (got %d)", G_max, t->groups);
     if (t->rotate != 0 && t->rotate != 1) return fail(GPMPPI_E_INVALID, "rotate must be 0 or 1");
@@ -878,6 +881,10 @@ gpmppi_status gpmppi_set_tuning(gpmppi_ctx *c, const gpmppi_tuning *t) {
     if (t->split && !split_admissible(c, t->waves))
         return fail(GPMPPI_E_UNSUPPORTED, "split outputs: the doubled grid of %d workgroups does not fit the device at once",
                     2 * ((c->params.K + 31) / 32));
+    if (t->waves == kPipeWaves && !rollout_pipe_admissible(c->params.precision, t->groups, c->Mpad))
+        return fail(GPMPPI_E_UNSUPPORTED,
+                    "waves = %d needs a BF16 form at M_pad = 1024 with the largest group count (here M_pad = %d)",
+                    kPipeWaves, c->Mpad);
     c->groups = t->groups;
     c->rotate = t->rotate;
     c->waves = t->waves;
@@ -910,8 +917,11 @@ gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
     gpmppi_tuning best{c->groups, c->rotate, 1, 0, c->waves, c->split, -1.0};
     for (int G = 1; G <= G_max; ++G)
         for (int rot = 0; rot <= 1; ++rot)
-            for (int nw = 4; nw <= 8; nw += 4)
-                for (int sp = 0; sp <= (G == 1 && split_admissible(c, nw) ? 1 : 0); ++sp) {
+            for (int nw = 4; nw <= kPipeWaves; nw += 4) {
+                // the wave-specialised shape walks W in one fixed order: rotate does not apply
+                if (nw == kPipeWaves && (rot != 0 || !rollout_pipe_admissible(c->params.precision, G, c->Mpad)))
+                    continue;
+                for (int sp = 0; sp <= (G == 1 && nw != kPipeWaves && split_admissible(c, nw) ? 1 : 0); ++sp) {
                     c->groups = G;
                     c->rotate = rot;
                     c->waves = nw;
@@ -929,6 +939,7 @@ gpmppi_status gpmppi_tune(gpmppi_ctx *c, const float *x0_d, const float *U_d, ui
                     }
                     if (best.ms < 0 || ms < best.ms) best = gpmppi_tuning{G, rot, 1, 0, nw, sp, ms};
                 }
+            }
     c->groups = best.groups;
     c->rotate = best.rotate;
     c->waves = best.waves;

@@ -23,6 +23,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOT_PD", -3: "E_HIP", -4: "E_NOMEM", 
 # status bits read by gpmppi_status_flags (GPMPPI_FLAG_* in gpmppi.h)
 FLAG_NONFINITE = 1
 FLAG_EXCHANGE_TIMEOUT = 2
+FLAG_PIPELINE_STALL = 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)

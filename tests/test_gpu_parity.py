@@ -418,20 +418,23 @@ def _form_margin_band(pr, tr_g, vtol):
             FB.obstacle_margin_bound(pr, x_g, x_p, sxy, exy))
 
 
+@pytest.mark.parametrize("waves", [None, 12])
 @pytest.mark.parametrize("prec", [B.BF16, B.BF16X3])
-def test_c2_bf16_forms_end_to_end(prec):
+def test_c2_bf16_forms_end_to_end(prec, waves):
     """The precision forms at c2's full size, end to end.  States, controls and GP means stay at the
     FP32 bar (the trajectory depends on the means only); on sampled samples each cost is within
     w_var sum_k |ds2_k| (its measured variance differences) plus the weights of the indicators whose
     margin lies within the measured margin differences; every cost is within 2 T w_var vtol plus the
     weights of the indicators whose own margin lies within the band that vtol allows (an indicator
     can differ from the oracle's only where the margin's sign can); U is within the form's stated
-    bar of the oracle's U."""
+    bar of the oracle's U.  waves = 12: the wave-specialised shape; None: the context's default."""
     import os
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.npz"))
     pr = W.make_config(2)
     vtol, utol = FORM_VAR_TOL[prec], FORM_U_TOL[prec]
     ctx = B.gpmppi_init(pr, prec)
+    if waves is not None:
+        B.gpmppi_set_tuning(ctx, B.gpmppi_get_tuning(ctx)["groups"], 0, waves)
     S_g, tr_g = gpu_rollout(pr, ctx=ctx)
     U_g, S2, _ = gpu_step(pr, ctx=ctx)
     np.testing.assert_array_equal(S2, S_g)
@@ -462,7 +465,7 @@ def test_c2_bf16_forms_end_to_end(prec):
     mb = float(max(bl.max(), bo.max()))
     eS_all = np.abs(S_g - g["S"])
     eU = np.abs(U_g - g["U"])
-    _print(f"c2 form={prec}", cost_sampled=eS_s.max(), cost_sampled_of_bound=(eS_s / bound_s).max(),
+    _print(f"c2 form={prec} waves={waves}", cost_sampled=eS_s.max(), cost_sampled_of_bound=(eS_s / bound_s).max(),
            cost_all=eS_all.max(), cost_all_of_bound=(eS_all / bound_all).max(), margin_band_max=mb,
            flagged=float((flip_all > 0).sum()), U=eU.max())
     assert np.all(eS_s <= bound_s), "sampled costs"
