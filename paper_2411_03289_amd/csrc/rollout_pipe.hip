@@ -45,10 +45,8 @@ namespace {
 constexpr int kPipeWalkers = 8;
 constexpr int kPipeStateWaves = 4;
 constexpr int kPipeNT = 32;     // column tiles of W at M_pad = 1024
-constexpr int kPipeIters = 34;  // iterations per walker and slot: pairs 15 - w and w
 constexpr int kPipeVRows = 4;   // slots of walker partials held in LDS
 constexpr int kPipeSpin = 1 << 20;
-constexpr int kPipeGeoSlots = 384;   // float4 slots of the LDS copy of the track and obstacles
 
 struct PipeSync {
     uint32_t ready[kPipeNT];
@@ -92,8 +90,10 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
     constexpr int B = 32 * G;
     const int Mpad = a.gp.Mpad;
     const int nslot = 2 * a.T;
-    // pairs hi = 15 - w then lo = w, the list repeated (the cursor reads it modulo 8 pairs)
-    const uint64_t two = (uint64_t)(kPipeNT / 2 - 1 - w) | ((uint64_t)w << 8);
+    // row-tile pairs hi = 15 - w then lo = w (34 iterations per slot for every walker), the
+    // list repeated (the cursor reads it modulo 8 pairs)
+    const int hi = kPipeNT / 2 - 1 - w, lo = w;
+    const uint64_t two = (uint64_t)hi | ((uint64_t)lo << 8);
     const uint64_t plist = two | (two << 16) | (two << 32) | (two << 48);
     const WRsrc<PREC> wr0 = w_rsrc<PREC>(a.gp, 0), wr1 = w_rsrc<PREC>(a.gp, 1);
     const int voff = 16 * lane;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
 
-    const int total = nslot * kPipeIters;   // even
+    const int total = nslot * (2 * hi + 2 * lo + 4);   // even
     for (int base = 0; base < total; base += 2) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
@@ -162,7 +162,7 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
             for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
             // the wave's last read of this tile in the slot: hand it back (its operand is in
             // registers: the products above waited for it)
-            if ((mc.n & 1) != 0 || mc.it > 2 * w + 1) {
+            if ((mc.n & 1) != 0 || mc.it > 2 * lo + 1) {
                 lds_order();
                 if (lane == 0) lds_add(&sy.freed[mc.it], 1u);
             }
@@ -262,6 +262,9 @@ __device__ __forceinline__ float pipe_gen(const GpDev &gp, int o, const float qs
                 L[lane] = make_uint4(lv[0], lv[1], lv[2], lv[3]);
                 L[64 + lane] = make_uint4(lv[4], lv[5], lv[6], lv[7]);
             }
+            // the group's mean products here and now: deferred into the next tile (the compiler
+            // would rotate them), its 16 kernel values would stay live across the waits
+            __asm__ __volatile__("" : "+v"(ms[gg]));
         }
         lds_order();
         if (lane == 0) lds_put(&sy.ready[jt], (uint32_t)e + 1u);
@@ -283,65 +286,6 @@ __device__ __forceinline__ float pipe_gen(const GpDev &gp, int o, const float qs
         return hl ? t1 : t0;
     }
     return t0;
-}
-
-// The chance-constraint geometry tables in LDS, where they fit: the polyline
-// segments [0, P), their 1 / |e|^2 packed four to a slot [P, P + ceil(P / 4)),
-// then the obstacles (P = 0 on a circular track).  The state waves read them as
-// broadcasts, which return in LDS time instead of the scalar cache's.
-__device__ __forceinline__ int geo_track_slots(const Geometry &geo) { return geo.path_kind != 0 ? geo.P : 0; }
-__device__ __forceinline__ int geo_lds_slots(const Geometry &geo) {
-    const int P = geo_track_slots(geo);
-    return P + (P + 3) / 4 + geo.n_obs;
-}
-
-template <int NT>
-__device__ __forceinline__ void stage_geometry(const Geometry &geo, v4f *tab) {
-    const int P = geo_track_slots(geo), ninv = (P + 3) / 4, n = geo_lds_slots(geo);
-    for (int i = threadIdx.x; i < n; i += NT) {
-        v4f v;
-        if (i < P) {
-            v = reinterpret_cast<const v4f *>(geo.seg)[i];
-        } else if (i < P + ninv) {
-            const int j = 4 * (i - P);
-            v = v4f{geo.seg_inv[j], j + 1 < P ? geo.seg_inv[j + 1] : 0.0f, j + 2 < P ? geo.seg_inv[j + 2] : 0.0f,
-                    j + 3 < P ? geo.seg_inv[j + 3] : 0.0f};
-        } else {
-            v = reinterpret_cast<const v4f *>(geo.obs)[i - P - ninv];
-        }
-        tab[i] = v;
-    }
-}
-
-// world_loop (the same arithmetic, in the same order) on the LDS tables.
-template <int LW, int B>
-__device__ __forceinline__ void world_loop_lds(const Geometry &geo, const v4f *tab, int oo, int wv, int sl, float Xs,
-                                               float Ys, float sa, float sb, float sc, float lmax, float *ored) {
-    const int P = geo_track_slots(geo);
-    if (oo == 0) {
-        if (geo.path_kind == 0) return;
-        const float *sinv = reinterpret_cast<const float *>(tab + P);
-        float best = INFINITY;
-#pragma unroll 4
-        for (int i = wv; i < P; i += LW) {
-            const v4f sgm = tab[i];
-            const float rx = Xs - sgm.x, ry = Ys - sgm.y;
-            float t = (rx * sgm.z + ry * sgm.w) * sinv[i];
-            t = fminf(fmaxf(t, 0.0f), 1.0f);
-            const float ex = rx - t * sgm.z, ey = ry - t * sgm.w;
-            best = fminf(best, ex * ex + ey * ey);
-        }
-        ored[wv * B + sl] = best;
-    } else {
-        const v4f *obs = tab + P + (P + 3) / 4;
-        float om = INFINITY;
-#pragma unroll 2
-        for (int j = wv; j < geo.n_obs; j += LW) {
-            const v4f ob = obs[j];
-            om = fminf(om, obstacle_margin(Xs - ob.x, Ys - ob.y, ob.z, sa, sb, sc, lmax, geo.z_p));
-        }
-        ored[(LW + wv) * B + sl] = om;
-    }
 }
 
 // Trace rows through buffer resources built per row block from the array's
@@ -414,8 +358,7 @@ __device__ __forceinline__ void add_stage_cost_var(const CostWeights &cw, float 
 
 template <int PREC, int G>
 __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g, int lane, unsigned char *lds,
-                                           PipeSync &sy, const float *vred, float *pred, float *ored,
-                                           const v4f *gtab) {
+                                           PipeSync &sy, const float *vred, float *pred, float *ored) {
     constexpr int B = 32 * G, LW = kPipeStateWaves;
     const int sl = lane % B;
     const int sg = blk * B + sl;
@@ -504,13 +447,8 @@ __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g,
         const float hh = 0.5f * (sa - sc);
         const float lmax = 0.5f * (sa + sc) + sqrtf(hh * hh + sb * sb);
         float *orow = ored + (k & 1) * 2 * LW * B;
-        if (geo_lds_slots(geo) <= kPipeGeoSlots) {
-            world_loop_lds<LW, B>(geo, gtab, 0, g, sl, X, Y, sa, sb, sc, lmax, orow);
-            world_loop_lds<LW, B>(geo, gtab, 1, g, sl, X, Y, sa, sb, sc, lmax, orow);
-        } else {
-            world_loop<LW, B>(geo, 0, g, sl, X, Y, sa, sb, sc, lmax, orow);
-            world_loop<LW, B>(geo, 1, g, sl, X, Y, sa, sb, sc, lmax, orow);
-        }
+        world_loop<LW, B>(geo, 0, g, sl, X, Y, sa, sb, sc, lmax, orow);
+        world_loop<LW, B>(geo, 1, g, sl, X, Y, sa, sb, sc, lmax, orow);
 
 #pragma unroll
         for (int d = 0; d < 4; ++d) qs[d] = q[d] * gp.scale[1][d];
@@ -564,18 +502,16 @@ __global__ __launch_bounds__(64 * (kPipeWalkers + kPipeStateWaves)) void rollout
     __shared__ float vred[kPipeVRows * kPipeWalkers * B];
     __shared__ float pred[2 * 2 * kPipeStateWaves * B];
     __shared__ float ored[2 * 2 * kPipeStateWaves * B];
-    __shared__ v4f gtab[kPipeGeoSlots];
     const int tid = threadIdx.x;
     if (tid < (int)(sizeof(PipeSync) / 4)) reinterpret_cast<uint32_t *>(&sy)[tid] = 0u;
     stage_alpha<kPipeWalkers + kPipeStateWaves>(a.gp, lds, G * kgroup_bytes<PREC>(a.gp.Mpad));   // both outputs
-    if (geo_lds_slots(a.geo) <= kPipeGeoSlots) stage_geometry<64 * (kPipeWalkers + kPipeStateWaves)>(a.geo, gtab);
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     if (w < kPipeWalkers)
         pipe_walker<PREC, G>(a, w, lane, lds, sy, vred);
     else
-        pipe_state<PREC, G>(a, blockIdx.x, w - kPipeWalkers, lane, lds, sy, vred, pred, ored, gtab);
+        pipe_state<PREC, G>(a, blockIdx.x, w - kPipeWalkers, lane, lds, sy, vred, pred, ored);
 }
 
 template <int PREC, int G>
