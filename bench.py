@@ -39,7 +39,8 @@ U_ERR_BAR = 1e-3
 # HBM bytes per rollout launch at this workload: rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (factors from a 1 GiB device copy in the same runs), taken
 # on the kernel sources whose SHA-256 is given; reported only while they match.
-KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd/csrc/gp_tiles.hpp",
+KERNEL_SOURCES = ["paper_2411_03289_amd/csrc/rollout.hip", "paper_2411_03289_amd/csrc/rollout_pipe.hip",
+                  "paper_2411_03289_amd/csrc/gp_tiles.hpp", "paper_2411_03289_amd/csrc/sample_step.hpp",
                   "paper_2411_03289_amd/csrc/device_common.hpp", "paper_2411_03289_amd/csrc/kernels.hpp",
                   "paper_2411_03289_amd/build.py"]
 MEASURED_TRAFFIC = {
@@ -367,7 +368,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per launch",
                      "hbm_frac": (traffic / (r["rollout_kernel_ms"] * 1e-3) / HBM_PEAK_BPS) if traffic else None,
-                     "kernel": "rollout_kernel", "flops_per_launch": flops_per_launch},
+                     "kernel": "rollout_pipe_kernel" if r["shape"]["waves"] == 12 else "rollout_kernel",
+                     "flops_per_launch": flops_per_launch},
         "forms": results,
         "speedup_vs_fp32": {n: results["fp32"]["ms_per_step"] / results[n]["ms_per_step"]
                             for n in results if "fp32" in results},

@@ -56,6 +56,10 @@ struct PipeSync {
     uint32_t stall;                 // a wait gave up
 };
 
+// The GP output of slot e: 0, 1, 1, 0, 0, 1, ... (step k takes output k % 2 first), so that
+// consecutive slots walk the same W where the steps meet and its blocks are still in L2.
+__device__ __forceinline__ int slot_output(int e) { return (e ^ (e >> 1)) & 1; }
+
 // Walkers that read column tile c in a slot: walker w reads c <= 31 - 2w.
 __device__ __forceinline__ uint32_t pipe_users(int c) { return c <= 17 ? 8u : (uint32_t)((31 - c) / 2 + 1); }
 
@@ -119,8 +123,8 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
     // zero block above it, so every iteration issues the same loads)
     auto fetch = [&](int r) {
         WRsrc<PREC> wr;
-        wr.h = (pe & 1) ? wr1.h : wr0.h;
-        wr.l = (pe & 1) ? wr1.l : wr0.l;
+        wr.h = slot_output(pe) ? wr1.h : wr0.h;
+        wr.l = slot_output(pe) ? wr1.l : wr0.l;
         const int b0 = pair_block(pc);
         load_wblock_rs<PREC>(ring[r][0], wr, pair_zero(pc) ? b0 + 1 : b0, voff);
         load_wblock_rs<PREC>(ring[r][1], wr, b0 + 1, voff);
@@ -399,8 +403,10 @@ __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g,
     auto variances = [&](int k, float &s20, float &s21) {
         for (int w = 0; w < kPipeWalkers; ++w) pipe_wait(&sy.vdone[w], (uint32_t)(2 * k + 2), sy);
         lds_order();
-        const float *r0 = vred + ((2 * k) % kPipeVRows) * kPipeWalkers * B;
-        const float *r1 = vred + ((2 * k + 1) % kPipeVRows) * kPipeWalkers * B;
+        // slot 2k holds output k % 2, slot 2k + 1 the other
+        const int first = k & 1;
+        const float *r0 = vred + ((2 * k + first) % kPipeVRows) * kPipeWalkers * B;
+        const float *r1 = vred + ((2 * k + 1 - first) % kPipeVRows) * kPipeWalkers * B;
         float v0 = 0.0f, v1 = 0.0f;
 #pragma unroll
         for (int w = 0; w < kPipeWalkers; ++w) {
@@ -417,9 +423,10 @@ __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g,
         const float2 u = sampled_control(np, k, sg, a.U[2 * k], a.U[2 * k + 1]);
         const float q[4] = {v, w_, u.x, u.y};
         float qs[4];
+        const int oa = k & 1, ob = 1 - oa;   // the outputs of slots 2k and 2k + 1
 #pragma unroll
-        for (int d = 0; d < 4; ++d) qs[d] = q[d] * gp.scale[0][d];
-        const float ms0 = pipe_gen<PREC, G>(gp, 0, qs, 2 * k, g, lane, lds, alds, sy);
+        for (int d = 0; d < 4; ++d) qs[d] = q[d] * gp.scale[oa][d];
+        const float msa = pipe_gen<PREC, G>(gp, oa, qs, 2 * k, g, lane, lds, alds, sy);
 
         if (k > 0) {   // step k - 1's variances: Sigma_k complete, its cost
             float s20, s21;
@@ -451,14 +458,14 @@ __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g,
         world_loop<LW, B>(geo, 1, g, sl, X, Y, sa, sb, sc, lmax, orow);
 
 #pragma unroll
-        for (int d = 0; d < 4; ++d) qs[d] = q[d] * gp.scale[1][d];
-        const float ms1 = pipe_gen<PREC, G>(gp, 1, qs, 2 * k + 1, g, lane, lds, alds, sy);
+        for (int d = 0; d < 4; ++d) qs[d] = q[d] * gp.scale[ob][d];
+        const float msb = pipe_gen<PREC, G>(gp, ob, qs, 2 * k + 1, g, lane, lds, alds, sy);
 
-        // the state waves meet: means and constraint partials of all four
+        // the state waves meet: means (row o: output o) and constraint partials of all four
         float *prow = pred + (k & 1) * 2 * LW * B;
         if (lane < B) {
-            prow[g * B + sl] = ms0;
-            prow[(LW + g) * B + sl] = ms1;
+            prow[(oa * LW + g) * B + sl] = msa;
+            prow[(ob * LW + g) * B + sl] = msb;
         }
         lds_order();
         met += LW;
