@@ -501,6 +501,8 @@ __device__ __forceinline__ void pipe_state(const RolloutArgs &a, int blk, int g,
     if (writer) a.costs[sg] = S_;
 }
 
+}  // namespace
+
 template <int PREC, int G>
 __global__ __launch_bounds__(64 * (kPipeWalkers + kPipeStateWaves)) void rollout_pipe_kernel(RolloutArgs a) {
     constexpr int B = 32 * G;
@@ -520,6 +522,8 @@ __global__ __launch_bounds__(64 * (kPipeWalkers + kPipeStateWaves)) void rollout
     else
         pipe_state<PREC, G>(a, blockIdx.x, w - kPipeWalkers, lane, lds, sy, vred, pred, ored);
 }
+
+namespace {
 
 template <int PREC, int G>
 hipError_t launch_pipe_t(const RolloutArgs &a, hipStream_t st) {
