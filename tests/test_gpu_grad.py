@@ -136,7 +136,7 @@ def test_autograd_function_returns_the_adjoint_gradient():
     pr2.log_ell = pr.log_ell + 0.1
     pr2.log_sf = pr.log_sf - 0.2
     Jd, dU, dle, dls, _ = _run(pr2, pr2.seed, C=4)
-    assert float(J) == pytest.approx(Jd[0], rel=1e-6)
+    assert float(J.detach()) == pytest.approx(Jd[0], rel=1e-6)
     np.testing.assert_allclose(U.grad.cpu().numpy(), dU, rtol=1e-6, atol=1e-9)
     np.testing.assert_allclose(le.grad.numpy(), dle, rtol=1e-6, atol=1e-9)
     np.testing.assert_allclose(ls.grad.numpy(), dls, rtol=1e-6, atol=1e-9)
