@@ -291,7 +291,8 @@ typedef struct {
 gpmppi_status gpmppi_tune(gpmppi_ctx *ctx, const float *x0_d, const float *U_d, uint64_t seed, int32_t reps,
                           gpmppi_tuning *chosen, void *stream);
 /* Output split: the number of polls each exchange wait makes before it gives
- * up.  A workgroup whose wait gives up (its partner is not running, for
+ * up (the wave-specialised rollout's hand-over waits take the same bound, see
+ * GPMPPI_FLAG_PIPELINE_STALL).  A workgroup whose wait gives up (its partner is not running, for
  * instance because other work holds the device) abandons the exchange,
  * computes its sample block alone from step 0 by the unsplit rollout's code
  * (the same results bit for bit, at about twice that workgroup's time) and
@@ -360,9 +361,11 @@ gpmppi_status gpmppi_philox(uint64_t seed, const uint32_t *ctr_d, int32_t n, uin
  *                                 gave up and its workgroup computed its block
  *                                 alone (results unchanged, time lost);
  *   GPMPPI_FLAG_PIPELINE_STALL    a hand-over wait inside a wave-specialised
- *                                 rollout workgroup (waves = 12) gave up, which
- *                                 only a defect can cause: that workgroup's
- *                                 costs are NaN.
+ *                                 rollout workgroup (waves = 12) gave up: that
+ *                                 workgroup's costs are NaN.  With the default
+ *                                 spin only a defect can cause it (the waits
+ *                                 depend on nothing outside the workgroup);
+ *                                 gpmppi_set_exchange_spin(ctx, -1) forces it.
  * Synchronises the device. */
 #define GPMPPI_FLAG_NONFINITE 1u
 #define GPMPPI_FLAG_EXCHANGE_TIMEOUT 2u

@@ -32,9 +32,10 @@
 // combine their partial means and constraint partials.
 //
 // Every hand-over is inside one workgroup, whose waves are resident together.
-// Every wait polls a bounded number of times; one that gives up marks the
-// workgroup, after which every wait returns at once, so the launch ends; the
-// workgroup's costs are then NaN and GPMPPI_FLAG_PIPELINE_STALL is set.
+// Every wait polls a bounded number of times (RolloutArgs::xspin, the exchange
+// spin of the context); one that gives up marks the workgroup, after which every
+// wait returns at once, so the launch ends; the workgroup's costs are then NaN
+// and GPMPPI_FLAG_PIPELINE_STALL is set.
 #include "gp_tiles.hpp"
 #include "sample_step.hpp"
 
@@ -46,7 +47,6 @@ constexpr int kPipeWalkers = 8;
 constexpr int kPipeStateWaves = 4;
 constexpr int kPipeNT = 32;     // column tiles of W at M_pad = 1024
 constexpr int kPipeVRows = 4;   // slots of walker partials held in LDS
-constexpr int kPipeSpin = 1 << 20;
 
 struct PipeSync {
     uint32_t ready[kPipeNT];
@@ -54,6 +54,7 @@ struct PipeSync {
     uint32_t vdone[kPipeWalkers];   // slots finished by each walker
     uint32_t sbar;                  // state-wave meeting counter
     uint32_t stall;                 // a wait gave up
+    int spin;                       // polls per wait before it gives up (RolloutArgs::xspin; < 0: none)
 };
 
 // The GP output of slot e: 0, 1, 1, 0, 0, 1, ... (step k takes output k % 2 first), so that
@@ -80,7 +81,8 @@ __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memor
 // Waits until *p >= target (bounded; see above).
 __device__ __forceinline__ void pipe_wait(const uint32_t *p, uint32_t target, PipeSync &sy) {
     if (__builtin_expect(lds_get(p) >= target, 1)) return;
-    for (int n = 0; n < kPipeSpin; ++n) {
+    const int polls = sy.spin;
+    for (int n = 0; n < polls; ++n) {
         __builtin_amdgcn_s_sleep(1);
         if (lds_get(p) >= target || lds_get(&sy.stall) != 0u) return;
     }
@@ -512,7 +514,8 @@ __global__ __launch_bounds__(64 * (kPipeWalkers + kPipeStateWaves)) void rollout
     __shared__ float pred[2 * 2 * kPipeStateWaves * B];
     __shared__ float ored[2 * 2 * kPipeStateWaves * B];
     const int tid = threadIdx.x;
-    if (tid < (int)(sizeof(PipeSync) / 4)) reinterpret_cast<uint32_t *>(&sy)[tid] = 0u;
+    if (tid < (int)(offsetof(PipeSync, spin) / 4)) reinterpret_cast<uint32_t *>(&sy)[tid] = 0u;
+    if (tid == 0) sy.spin = a.xspin;
     stage_alpha<kPipeWalkers + kPipeStateWaves>(a.gp, lds, G * kgroup_bytes<PREC>(a.gp.Mpad));   // both outputs
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
