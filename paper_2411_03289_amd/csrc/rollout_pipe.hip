@@ -8,7 +8,10 @@
 //    Walker w takes the row-tile pairs 15 - w and w of W (34 iterations of two
 //    32x32 blocks, the same count for every walker), always columns descending,
 //    for the output slots e = 2 k + o of all steps one after another; W streams
-//    through a register ring that runs on from one slot into the next.
+//    through a register ring three iterations deep that runs on from one slot
+//    into the next.  The walkers issue at a raised wave priority, so that a
+//    walker's next matrix-core product goes ahead of the state waves' vector
+//    instructions on the same SIMD.
 //  * Waves 8-11, the state waves, keep the sample state (every state wave all B
 //    samples, as every wave of rollout_kernel does), draw the noise, generate
 //    the kernel vectors (the other shapes' matrix-core generation, bit for bit
@@ -107,8 +110,8 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) kgrp[gg] = lds + gg * kgroup_bytes<PREC>(Mpad);
 
-    WBlock<PREC> ring[2][2];
-    KOp<PREC> kb[2][G];
+    WBlock<PREC> ring[3][2];   // W blocks of the next three iterations
+    KOp<PREC> kb[G];           // k operand of the current iteration
     v16f acc[2][G];
     float sq[G];
 #pragma unroll
@@ -151,21 +154,25 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
     };
     fetch(0);
     fetch(1);
+    fetch(2);
     if (nslot > 0) need(mc.it, 0);
     lds_order();
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[0][gg], kgrp[gg], mc.it, lane, Mpad);
+    for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[gg], kgrp[gg], mc.it, lane, Mpad);
 
-    const int total = nslot * (2 * hi + 2 * lo + 4);   // even
-    for (int base = 0; base < total; base += 2) {
+    // the ring slot of an iteration is its index mod 3; the fetches past the last iteration
+    // read W blocks of the repeated pair list and are never used
+    const int total = nslot * (2 * hi + 2 * lo + 4);
+    for (int base = 0; base < total; base += 3) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < 3; ++r) {
+            if (base + r >= total) break;
             if (!pair_zero(mc)) {
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[r][gg]);
+                for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[0][gg], ring[r][0], kb[gg]);
             }
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[r][gg]);
+            for (int gg = 0; gg < G; ++gg) mma_block<PREC>(acc[1][gg], ring[r][1], kb[gg]);
             // the wave's last read of this tile in the slot: hand it back (its operand is in
             // registers: the products above waited for it)
             if ((mc.n & 1) != 0 || mc.it > 2 * lo + 1) {
@@ -179,7 +186,7 @@ __device__ __forceinline__ void pipe_walker(const RolloutArgs &a, int w, int lan
             if (ne < nslot) need(mc.it, ne);
             lds_order();
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[1 - r][gg], kgrp[gg], mc.it, lane, Mpad);
+            for (int gg = 0; gg < G; ++gg) load_kop<PREC>(kb[gg], kgrp[gg], mc.it, lane, Mpad);
             if (__builtin_expect(pair_end, 0)) {
 #pragma unroll
                 for (int gg = 0; gg < G; ++gg) {
@@ -520,9 +527,10 @@ __global__ __launch_bounds__(64 * (kPipeWalkers + kPipeStateWaves)) void rollout
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
-    if (w < kPipeWalkers)
+    if (w < kPipeWalkers) {
+        __builtin_amdgcn_s_setprio(1);
         pipe_walker<PREC, G>(a, w, lane, lds, sy, vred);
-    else
+    } else
         pipe_state<PREC, G>(a, blockIdx.x, w - kPipeWalkers, lane, lds, sy, vred, pred, ored);
 }
 
