@@ -388,12 +388,18 @@ __global__ __launch_bounds__(64 * NW) void rollout_kernel(RolloutArgs a) {
         __hip_atomic_store(a.repair + blockIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The problems of a batch, read-only for the whole launch: through the constant
+// address space their fields come in by scalar loads the compiler may repeat
+// where they are used, as a kernel argument's do, instead of vector loads kept
+// live in registers across the item (which spilled the eight-wave shapes).
+typedef const RolloutArgs __attribute__((address_space(4))) ConstRolloutArgs;
+
 // Persistent rollout of many independent problems: every workgroup takes
 // (problem, sample block) items from a shared counter until the list (sorted
 // longest first) is exhausted.  Results do not depend on which workgroup
 // runs an item.  *counter must be 0 at launch.
 template <int PREC, int G, int NW>
-__global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(const RolloutArgs *probs, const int2 *items,
+__global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(ConstRolloutArgs *probs, const int2 *items,
                                                                  int n_items, uint32_t *counter) {
     using S = Shapes<PREC, G, NW>;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(64 * NW) void rollout_batch_kernel(const RolloutArg
         const int2 pb = items[it];
         const int p = __builtin_amdgcn_readfirstlane(pb.x);
         const int b = __builtin_amdgcn_readfirstlane(pb.y);
-        rollout_block<PREC, G, NW>(probs[p], b, lds, pred, ored, vred);
+        rollout_block<PREC, G, NW>(*(const RolloutArgs *)&probs[p], b, lds, pred, ored, vred);
     }
 }
 
@@ -557,8 +563,8 @@ static hipError_t launch_rollout_batch_t(const RolloutArgs *probs, const int2 *i
     const size_t lds = dyn_lds_bytes<PREC, G>(Mpad_max);
     hipError_t e = set_lds(rollout_batch_kernel<PREC, G, NW>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rollout_batch_kernel<PREC, G, NW>), dim3(grid), dim3(64 * NW), lds, st, probs, items, n_items,
-                       counter);
+    hipLaunchKernelGGL((rollout_batch_kernel<PREC, G, NW>), dim3(grid), dim3(64 * NW), lds, st,
+                       (ConstRolloutArgs *)probs, items, n_items, counter);
     return hipGetLastError();
 }
 
