@@ -179,6 +179,41 @@ def test_goal_terms_closed_form():
     np.testing.assert_allclose(S2 - base, 0.2 * dg2.sum() + 1.5, rtol=1e-12)
 
 
+def test_step2_tightening_matches_monte_carlo_along_the_nominal_controls():
+    # Alg. 1 Step 2 propagates Sigma_XY (Eq. 10) along the nominal controls clip(U).  With the GP's
+    # training points far from every query its mean is exactly 0 and its variance the closed form
+    # sf^2 + sn^2, so the stochastic model is the Euler step driven by clip(U) with that velocity
+    # noise; with small noise the spread of many such rollouts approaches the propagated
+    # covariance.  Nothing here comes from the oracle's rollout.
+    from oracle import dynamics as D
+    # the turn-rate noise dominates, so the spread also runs through the heading (the Jacobian's
+    # coupling of position to heading), not only through the speed
+    pr = W.small_problem(K=40, T=20, M=20, n_obs=0, path="eight", seed_data=17, U_scale=1.0)
+    pr.Z = pr.Z + 1.0e3
+    pr.y = np.zeros_like(pr.y)
+    pr.log_sf = np.log([1.0e-4, 6.0e-3])
+    pr.log_sn = np.log([5.0e-5, 1.0e-3])
+    s2 = np.exp(2 * pr.log_sf) + np.exp(2 * pr.log_sn)
+    nom = mppi.nominal_tightening(pr, pr.x0, pr.U0)
+    p = pr.params
+    u = np.clip(pr.U0, p["u_min"], p["u_max"])
+    rng = np.random.Generator(np.random.PCG64(21))
+    n = 200_000
+    x = np.tile(np.asarray(pr.x0, float), (n, 1))
+    for k in range(pr.T):
+        m = rng.normal(0.0, np.sqrt(s2), size=(n, 2))
+        x = D.euler_step(x, np.tile(u[k], (n, 1)), m, p["dt"], p["tau_v"], p["tau_w"])
+        if k == 0:   # the position of step 1 follows the noise-free initial velocity
+            np.testing.assert_array_equal(nom[1], 0.0)
+            assert np.ptp(x[:, :2], axis=0).max() == 0.0
+            continue
+        C = np.cov(x[:, :2].T)
+        sx, sy = np.sqrt(nom[k + 1, 0]), np.sqrt(nom[k + 1, 2])
+        got = np.array([C[0, 0] / sx**2, C[0, 1] / (sx * sy), C[1, 1] / sy**2])
+        want = np.array([1.0, nom[k + 1, 1] / (sx * sy), 1.0])
+        np.testing.assert_allclose(got, want, atol=0.02, err_msg=f"step {k + 1}")
+
+
 def test_step2_tightening_uses_the_nominal_covariance():
     pr = W.small_problem(K=40, T=10, M=20, n_obs=6, path="eight", seed_data=17, U_scale=1.0)
     pr.params["tighten"] = 1
