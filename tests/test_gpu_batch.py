@@ -33,7 +33,7 @@ def _pack(problems):
     return x0, U
 
 
-@pytest.mark.parametrize("precision", [B.FP32, B.BF16])
+@pytest.mark.parametrize("precision", [B.FP32, B.BF16, B.BF16X3])
 def test_batch_step_equals_unbatched_runs(precision):
     t = torch()
     ps = _problems()
